@@ -1,0 +1,156 @@
+"""Seeded synthetic inputs: run parameters and initial fields.
+
+This module holds no arithmetic of the lattice Boltzmann method.  It only
+chooses parameter values (those the paper prints, in Sec. III.B and Sec. IV,
+and the documented readings where it prints none) and draws initial fields
+with numpy's PCG64 generator.  Both the GPU path and the CPU oracle are fed
+the very same host arrays from here.
+
+The coexistence densities and the critical temperature below are numbers,
+not computed here: ``tests/golden/make_coexistence.py`` derives them from the
+oracle's Peng-Robinson EOS (Eq. 56) by the Maxwell equal-area construction,
+stores them in ``tests/golden/coexistence_pr.json``, and a test checks that the
+table here matches that file.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# Peng-Robinson parameters of Sec. III.B (Eq. 56)
+A_PR = 3.0 / 49.0
+B_PR = 2.0 / 21.0
+R_GAS = 1.0
+OMEGA = 0.344
+
+# critical temperature and Maxwell coexistence at T = 0.86 Tc (oracle values)
+TC = 0.10938300611120137
+T_SAT = 0.86 * TC
+RHO_V = 0.3796789993997201
+RHO_L = 6.498945763287883
+
+BC_PERIODIC, BC_WALL, BC_OPEN = 0, 1, 2
+LAMBDA_CONST, LAMBDA_RHO_CV_CHI = 0, 1
+THERMAL_IMPROVED, THERMAL_COMPROMISED = 0, 1
+FP64, FP32, FP32_SHIFTED, FP16_SHIFTED = 0, 1, 2, 3
+
+# kinematic viscosity nu = 0.1 (Sec. IV.A) -> s_nu = 1 / (3 nu + 1/2)
+NU = 0.1
+S_NU = 1.0 / (3.0 * NU + 0.5)
+# flow MRT rates: conserved moments 1.0, energy-like 1.25, heat-flux-like 1.1,
+# stress S_NU (reading of the cited flow model; the paper gives only nu)
+S_F_DEFAULT = (1.0, 1.25, 1.25, 1.0, 1.1, 1.0, 1.1, S_NU, S_NU)
+# thermal MRT rates: s3 = s5 = 1 (Sec. IV.A), the rest 1.0 (not given)
+S_G_DEFAULT = (1.0,) * 9
+# mechanical-stability constant of the flow forcing scheme (reading; chosen
+# once from the flat-interface coexistence test and then frozen)
+SIGMA_DEFAULT = 0.105
+CV = 5.0
+LAMBDA_D2 = 2.0 / 3.0   # constant conductivity of the D^2-law test
+CHI_BUBBLE = 0.06       # lambda = rho c_V chi of the boiling test
+
+
+def base_config(nx: int, ny: int, **over) -> dict:
+    cfg = dict(
+        a=A_PR, b=B_PR, R=R_GAS, omega=OMEGA, cv=CV,
+        lambda0=LAMBDA_D2, chi=CHI_BUBBLE,
+        s_f=list(S_F_DEFAULT), s_g=list(S_G_DEFAULT),
+        G=-1.0, sigma=SIGMA_DEFAULT, gx=0.0, gy=0.0,
+        T_bc=[T_SAT] * 4, T_hot=T_SAT, rho_ref=0.0, T_ref=0.0,
+        rho_v=RHO_V, rho_l=RHO_L,
+        nx=int(nx), ny=int(ny), bc=[BC_PERIODIC] * 4,
+        hot_x0=0, hot_x1=0, lambda_mode=LAMBDA_CONST,
+        thermal_model=THERMAL_IMPROVED, precision=FP64, flags=0,
+    )
+    cfg.update(over)
+    return cfg
+
+
+def tanh_profile(dist, width, rho_in, rho_out):
+    """rho = (rho_in + rho_out)/2 - (rho_in - rho_out)/2 tanh(2 dist / width),
+    with dist > 0 outside the liquid."""
+    return 0.5 * (rho_in + rho_out) - 0.5 * (rho_in - rho_out) * np.tanh(
+        2.0 * dist / width)
+
+
+def droplet_fields(nx, ny, radius, width=5.0, T=T_SAT, cx=None, cy=None,
+                   rho_l=RHO_L, rho_v=RHO_V):
+    cx = nx / 2.0 if cx is None else cx
+    cy = ny / 2.0 if cy is None else cy
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    r = np.sqrt((x - cx) ** 2 + (y - cy) ** 2)
+    rho = tanh_profile(r - radius, width, rho_l, rho_v)
+    z = np.zeros((ny, nx))
+    return dict(rho=rho, ux=z.copy(), uy=z.copy(), T=np.full((ny, nx), T))
+
+
+# ------------------------------------------------------------ workloads --
+
+def static_droplet(nx=100, ny=100, radius=25.0):
+    """Static droplet: periodic, T = 0.86 Tc, tanh profile of width 5."""
+    cfg = base_config(nx, ny)
+    return cfg, droplet_fields(nx, ny, radius)
+
+
+def evaporation(n=300, radius=50.0, T_b_over_Ts=1.1, precision=FP64):
+    """Droplet at T_sat in vapour at T_sat; all four sides open with the
+    fixed temperature T_b = 1.1 T_sat; constant lambda; no gravity."""
+    Tb = T_b_over_Ts * T_SAT
+    cfg = base_config(n, n, bc=[BC_OPEN] * 4, T_bc=[Tb] * 4,
+                      precision=precision)
+    return cfg, droplet_fields(n, n, radius)
+
+
+def bubble(nx=400, ny=800, pool=600, hot_width=40, T_hot_over_Ts=1.2,
+           g=3e-5, precision=FP64):
+    """Liquid pool below vapour at T_sat; periodic x; no-slip walls at the
+    bottom (T_sat with a centred hot spot) and top (T_sat); gravity -g in y;
+    lambda = rho c_V chi with chi = 0.06."""
+    x0 = nx // 2 - hot_width // 2
+    cfg = base_config(nx, ny, bc=[BC_PERIODIC, BC_PERIODIC, BC_WALL, BC_WALL],
+                      T_bc=[T_SAT] * 4, hot_x0=x0, hot_x1=x0 + hot_width,
+                      T_hot=T_hot_over_Ts * T_SAT, gy=-g,
+                      lambda_mode=LAMBDA_RHO_CV_CHI, precision=precision)
+    y = np.mgrid[0:ny, 0:nx][0].astype(np.float64)
+    rho = tanh_profile(y - (pool - 0.5), 5.0, RHO_L, RHO_V)
+    z = np.zeros((ny, nx))
+    return cfg, dict(rho=rho, ux=z.copy(), uy=z.copy(),
+                     T=np.full((ny, nx), T_SAT))
+
+
+def spinodal(n=4096, seed=4400, precision=FP64, rho_ref=None):
+    """Periodic n x n; rho = mean coexistence density (1 + U(-0.01, 0.01)),
+    T = T_sat (1 + U(-0.005, 0.005)), u = 0."""
+    rng = np.random.default_rng(seed)
+    mean = 0.5 * (RHO_L + RHO_V)
+    rho = mean * (1.0 + rng.uniform(-0.01, 0.01, size=(n, n)))
+    T = T_SAT * (1.0 + rng.uniform(-0.005, 0.005, size=(n, n)))
+    cfg = base_config(n, n, precision=precision,
+                      rho_ref=mean if rho_ref is None else rho_ref,
+                      T_ref=T_SAT)
+    z = np.zeros((n, n))
+    return cfg, dict(rho=rho, ux=z, uy=z.copy(), T=T)
+
+
+def batch_sizes(count=256, seed=1709):
+    """Square sizes uniform in {64, 96, ..., 512} and boundary temperatures
+    uniform in [1.02, 1.2] T_sat, drawn from one seeded generator."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.choice(np.arange(64, 513, 32), size=count)
+    tb = rng.uniform(1.02, 1.2, size=count)
+    return [int(s) for s in sizes], [float(t) for t in tb]
+
+
+def batch_cases(count=256, seed=1709, precision=FP32):
+    """The batched evaporation sweep: one evaporation case per draw, droplet
+    radius 0.2 x grid size."""
+    sizes, tb = batch_sizes(count, seed)
+    return [evaporation(n, 0.2 * n, t, precision=precision)
+            for n, t in zip(sizes, tb)]
+
+
+def random_rates(seed, lo=0.6, hi=1.6):
+    """Distinct MRT rates for parity runs (so that no moment path is masked
+    by a rate of exactly 1)."""
+    rng = np.random.default_rng(seed)
+    return [float(v) for v in rng.uniform(lo, hi, 9)], [
+        float(v) for v in rng.uniform(lo, hi, 9)]
