@@ -1,0 +1,176 @@
+/*
+ * lbpc.h -- C ABI of the MI355X (gfx950) library for the coupled
+ * pseudopotential-multiphase / improved-thermal MRT lattice Boltzmann time
+ * step of Li, Zhou & Yan, "Improved thermal lattice Boltzmann model for
+ * simulation of liquid-vapor phase change" (arXiv:1709.04400).
+ *
+ * What one step computes, on every node of an nx x ny D2Q9 lattice (lattice
+ * units, dx = dt = c = 1, c_s^2 = 1/3):
+ *   - density rho, momentum j and temperature T = sum_a g_a (Sec. III.A);
+ *   - the Peng-Robinson p_EOS(rho, T) of Eq. (56) and the pseudopotential
+ *     psi = sqrt(2 (p_EOS - rho c_s^2) / G), always in FP64;
+ *   - the interaction force -G psi(x) sum_a w_a psi(x + e_a) e_a plus the
+ *     buoyancy (rho - rho_ave) g of Sec. IV.B; v = (j + F/2) / rho;
+ *   - the flow MRT collision with the pseudopotential forcing scheme the
+ *     paper adopts for the flow field (Sec. III.B, cited there);
+ *   - the thermal source phi of Eq. (28) (its underlined terms) from
+ *     isotropic differences, S0 = phi + (phi - phi_prev)/2 (Eq. 46 with the
+ *     backward difference of Sec. III.B);
+ *   - the improved thermal MRT collision: Eqs. (45), (46), (53), (54), (55);
+ *   - streaming, Eq. (47), with periodic, wall (halfway bounce-back and
+ *     anti-bounce-back Dirichlet T, optional hot spot) or open (zero-gradient
+ *     flow, fixed T) sides.
+ *
+ * Ownership: the caller owns every host array and the device workspace
+ * (sized by lbpc_workspace_bytes, at least 256-byte aligned, alive until
+ * lbpc_destroy returns).  The library owns the handle.  No call aborts;
+ * every call returns an lbpc_status, and lbpc_last_error gives a message.
+ * Calls on one handle are not thread-safe; different handles are
+ * independent.  Device work is enqueued on the stream given at creation.
+ */
+#ifndef LBPC_H
+#define LBPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbpc_handle lbpc_handle;
+
+typedef enum {
+  LBPC_OK = 0,
+  LBPC_ERR_ARG = -1,         /* invalid argument or configuration */
+  LBPC_ERR_HIP = -2,         /* a HIP runtime call failed */
+  LBPC_ERR_OOM = -3,         /* workspace too small / host allocation */
+  LBPC_ERR_STATE = -4,       /* call out of order (e.g. step before init) */
+  LBPC_ERR_NUMERIC = -5,     /* non-finite or invalid state detected */
+  LBPC_ERR_UNSUPPORTED = -6  /* option not available on this path */
+} lbpc_status;
+
+/* storage precision of the distributions (arithmetic: FP64 for FP64, FP32
+ * otherwise; psi(rho, T) and the diagnostic sums are always FP64).  The
+ * shifted forms store f_a - w_a rho_ref and g_a - wg_a T_ref, with w the
+ * D2Q9 weights and wg = (5/9, 1/18, ..., 1/18) the rest equilibrium of
+ * Eq. (53). */
+typedef enum {
+  LBPC_FP64 = 0,
+  LBPC_FP32 = 1,
+  LBPC_FP32_SHIFTED = 2,
+  LBPC_FP16_SHIFTED = 3
+} lbpc_precision;
+
+/* side kinds; sides are ordered x-, x+, y-, y+.  Opposite sides are both
+ * periodic or both not. */
+typedef enum {
+  LBPC_BC_PERIODIC = 0,
+  LBPC_BC_WALL = 1, /* no-slip halfway bounce-back; T fixed (anti-bounce-back) */
+  LBPC_BC_OPEN = 2  /* zero-gradient flow; incoming g at rest equilibrium T */
+} lbpc_bc;
+
+typedef enum { LBPC_LAMBDA_CONST = 0, LBPC_LAMBDA_RHO_CV_CHI = 1 } lbpc_lambda;
+/* Sec. IV: the improved model, and the "compromised" one without
+ * Eqs. (54)-(55) and without the (phi - phi_prev)/2 term */
+typedef enum {
+  LBPC_THERMAL_IMPROVED = 0,
+  LBPC_THERMAL_COMPROMISED = 1
+} lbpc_thermal_model;
+
+/* Ghost rule at a non-periodic side, used by every stencil: a neighbour
+ * outside the lattice takes rho and psi of the nearest lattice node, v = 0
+ * at a wall (v of that node at an open side) and T of the crossed side (y
+ * side first at corners; the y- wall has T_hot on hot_x0 <= x < hot_x1).
+ *
+ * Field order and types match the oracle's configuration struct exactly
+ * (a test compares the two layouts). */
+typedef struct lbpc_config {
+  double a, b, R, omega;  /* Peng-Robinson EOS, Eq. (56) */
+  double cv;              /* specific heat at constant volume */
+  double lambda0;         /* conductivity for LBPC_LAMBDA_CONST */
+  double chi;             /* lambda = rho c_V chi for LBPC_LAMBDA_RHO_CV_CHI */
+  double s_f[9];          /* flow MRT rates, moments (rho,e,eps,jx,qx,jy,qy,pxx,pxy) */
+  double s_g[9];          /* thermal MRT rates, Eq. (43); k = (1/s_g[3]-1/2)/3 */
+  double G;               /* interaction strength, < 0 */
+  double sigma;           /* forcing-scheme constant (flow model) */
+  double gx, gy;          /* gravity for the buoyancy (rho - rho_ave) g */
+  double T_bc[4];         /* side temperatures (wall / open sides) */
+  double T_hot;           /* hot-spot temperature on the y- wall */
+  double rho_ref, T_ref;  /* references of the shifted storage forms */
+  double rho_v, rho_l;    /* coexistence densities for the radius diagnostic */
+  int32_t nx, ny;         /* lattice size, each >= 4 */
+  int32_t bc[4];          /* lbpc_bc per side */
+  int32_t hot_x0, hot_x1; /* hot-spot columns */
+  int32_t lambda_mode;    /* lbpc_lambda */
+  int32_t thermal_model;  /* lbpc_thermal_model */
+  int32_t precision;      /* lbpc_precision */
+  uint32_t flags;         /* must be 0 (the oracle's test-only flags) */
+} lbpc_config;
+
+/* FP64 sums over the lattice at the current time level */
+typedef struct lbpc_diag {
+  double mass;         /* sum rho */
+  double sum_T;        /* sum T */
+  double sum_rhocvT;   /* sum rho c_V T */
+  double liquid_area;  /* sum clamp((rho - rho_v)/(rho_l - rho_v), 0, 1) */
+  double radius;       /* sqrt(liquid_area / pi) */
+  double radius_count; /* sqrt(#{rho > (rho_l + rho_v)/2} / pi) */
+  double max_speed;    /* max |v| (FP64 max over nodes) */
+  double sum_S0;       /* reserved (0) */
+  double sum_Fx, sum_Fy; /* reserved (0) */
+  int64_t step;        /* steps taken since lbpc_init_fields */
+  int32_t nonfinite;   /* 1 if a non-finite rho or T was seen */
+  int32_t pad;
+} lbpc_diag;
+
+/* Device bytes the caller must provide for this configuration. */
+lbpc_status lbpc_workspace_bytes(const lbpc_config *cfg, size_t *bytes);
+
+/* Validates cfg and binds the workspace and stream (hipStream_t, may be
+ * NULL for the null stream).  Nothing is launched.  On failure *out is NULL. */
+lbpc_status lbpc_create(const lbpc_config *cfg, void *dev_workspace,
+                        size_t workspace_bytes, void *hip_stream,
+                        lbpc_handle **out);
+
+/* Initial fields: host FP64 arrays, row-major [ny][nx], copied (the call
+ * returns after the copy).  Sets f = f^eq(rho, u), g = g^eq(T, u) (Eq. 53
+ * moments mapped back by M^-1), rho_ave = mean rho, step = 0, and marks
+ * phi_prev as unset (the first step uses phi_prev = phi).  Rejects rho <= 0,
+ * rho >= 1/b, T <= 0, a negative psi^2 or non-finite values (LBPC_ERR_ARG). */
+lbpc_status lbpc_init_fields(lbpc_handle *h, const double *rho,
+                             const double *ux, const double *uy,
+                             const double *T);
+
+/* Enqueues n >= 0 coupled time steps on the stream and returns without
+ * waiting.  A non-finite state is reported by the next synchronising call. */
+lbpc_status lbpc_step(lbpc_handle *h, int64_t n);
+
+/* Waits for the stream; writes rho, v = (j + F/2)/rho and T at the current
+ * time level into host FP64 arrays [ny][nx] (any pointer may be NULL).
+ * Returns LBPC_ERR_NUMERIC if a non-finite value is present. */
+lbpc_status lbpc_get_rho_u_T(lbpc_handle *h, double *rho, double *ux,
+                             double *uy, double *T);
+
+/* Waits for the stream and fills *out. */
+lbpc_status lbpc_get_diag(lbpc_handle *h, lbpc_diag *out);
+
+/* Canonical state {f(t) [9][ny][nx], g(t) [9][ny][nx], phi(t-1) [ny][nx]}
+ * as FP64, plus phi_valid, rho_ave and step: lbpc_state_bytes gives the
+ * host buffer size; save waits for the stream. */
+lbpc_status lbpc_state_bytes(const lbpc_handle *h, size_t *bytes);
+lbpc_status lbpc_save_state(lbpc_handle *h, void *host, size_t bytes);
+lbpc_status lbpc_load_state(lbpc_handle *h, const void *host, size_t bytes);
+
+/* Waits for outstanding work, then frees the handle (NULL-safe).  The
+ * workspace stays the caller's. */
+void lbpc_destroy(lbpc_handle *h);
+
+/* Message of the last failure on h (or of the calling thread's last failed
+ * lbpc_create / lbpc_workspace_bytes when h is NULL).  Never NULL. */
+const char *lbpc_last_error(const lbpc_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBPC_H */

@@ -1,0 +1,469 @@
+// lbpc_api.cpp -- host runtime behind include/lbpc.h: configuration checks,
+// derived constants, the workspace plan, state bookkeeping (ping-pong
+// buffer, fresh / phi_prev flags) and the launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbpc.h"
+#include "lbpc_device.h"
+
+namespace lbpc {
+hipError_t launch_step(const StepParams& p, int prec, hipStream_t s);
+hipError_t launch_init(const StepParams& p, int prec, const double* in,
+                       hipStream_t s);
+hipError_t launch_macro(const StepParams& p, int prec, double* io,
+                        hipStream_t s);
+hipError_t launch_diag(const StepParams& p, const double* io, double rho_v,
+                       double rho_l, double* partial, double* out,
+                       hipStream_t s);
+hipError_t launch_canon(const StepParams& p, int prec, int which, double* out,
+                        hipStream_t s);
+hipError_t launch_load(const StepParams& p, int prec, int which,
+                       const double* in, hipStream_t s);
+hipError_t launch_phi_out(const StepParams& p, int prec, double* out,
+                          hipStream_t s);
+hipError_t launch_phi_in(const StepParams& p, int prec, const double* in,
+                         hipStream_t s);
+int diag_blocks(long long N);
+}  // namespace lbpc
+
+using lbpc::StepParams;
+
+namespace {
+
+thread_local std::string g_err = "";
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+size_t store_bytes(int prec) {
+  return prec == LBPC_FP64 ? 8 : (prec == LBPC_FP16_SHIFTED ? 2 : 4);
+}
+size_t compute_bytes(int prec) { return prec == LBPC_FP64 ? 8 : 4; }
+
+struct Layout {
+  size_t dist[2][2];  // offsets of f / g of buffer 0 / 1
+  size_t phi, scratch, partial, diag_out;
+  size_t total;
+};
+
+Layout plan(const lbpc_config& c) {
+  Layout L;
+  const size_t N = (size_t)c.nx * (size_t)c.ny;
+  const size_t dbytes = align_up(9 * N * store_bytes(c.precision));
+  size_t off = 0;
+  for (int b = 0; b < 2; ++b)
+    for (int k = 0; k < 2; ++k) {
+      L.dist[b][k] = off;
+      off += dbytes;
+    }
+  L.phi = off;
+  off += align_up(N * compute_bytes(c.precision));
+  L.scratch = off;
+  off += align_up(5 * N * sizeof(double));
+  L.partial = off;
+  off += align_up((size_t)lbpc::diag_blocks((long long)N) * 8 * sizeof(double));
+  L.diag_out = off;
+  off += align_up(8 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+double pr_Tc(const lbpc_config& c) {
+  return 0.0778 * c.a / (0.45724 * c.b * c.R);
+}
+double pr_kappa(double w) { return 0.37464 + 1.54226 * w - 0.26992 * w * w; }
+
+double host_psi2(const lbpc_config& c, double rho, double T) {
+  const double Tc = pr_Tc(c), k = pr_kappa(c.omega);
+  const double s = 1.0 + k * (1.0 - std::sqrt(T / Tc));
+  const double p = rho * c.R * T / (1.0 - c.b * rho) -
+                   c.a * s * s * rho * rho /
+                       (1.0 + 2.0 * c.b * rho - c.b * c.b * rho * rho);
+  return 2.0 * (p - rho * (1.0 / 3.0)) / c.G;
+}
+
+const char* check_config(const lbpc_config* c) {
+  if (!c) return "config is NULL";
+  if (c->nx < 4 || c->ny < 4) return "nx and ny must be >= 4";
+  if ((long long)c->nx * (long long)c->ny > (1LL << 31))
+    return "lattice larger than 2^31 nodes";
+  for (int i = 0; i < 4; ++i)
+    if (c->bc[i] < 0 || c->bc[i] > 2) return "bc must be 0, 1 or 2";
+  if ((c->bc[0] == LBPC_BC_PERIODIC) != (c->bc[1] == LBPC_BC_PERIODIC))
+    return "x sides must be both periodic or both not";
+  if ((c->bc[2] == LBPC_BC_PERIODIC) != (c->bc[3] == LBPC_BC_PERIODIC))
+    return "y sides must be both periodic or both not";
+  for (int i = 0; i < 9; ++i)
+    if (!(c->s_f[i] > 0.0 && c->s_f[i] < 2.0) ||
+        !(c->s_g[i] > 0.0 && c->s_g[i] < 2.0))
+      return "relaxation rates must lie in (0, 2)";
+  if (!(c->G < 0.0)) return "G must be negative";
+  if (!(c->a > 0.0 && c->b > 0.0 && c->R > 0.0 && c->cv > 0.0))
+    return "a, b, R and cv must be positive";
+  if (c->lambda_mode != LBPC_LAMBDA_CONST &&
+      c->lambda_mode != LBPC_LAMBDA_RHO_CV_CHI)
+    return "unknown lambda_mode";
+  if (c->thermal_model != LBPC_THERMAL_IMPROVED &&
+      c->thermal_model != LBPC_THERMAL_COMPROMISED)
+    return "unknown thermal_model";
+  if (c->precision < LBPC_FP64 || c->precision > LBPC_FP16_SHIFTED)
+    return "unknown precision";
+  return nullptr;
+}
+
+}  // namespace
+
+struct lbpc_handle {
+  lbpc_config cfg;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  Layout L;
+  StepParams base;
+  int cur;        // buffer holding the state
+  int fresh;      // state buffer holds pre-collision f(t)
+  int phi_valid;  // phi history holds phi(t-1)
+  int initialised;
+  int64_t step;
+  double rho_ave;
+  std::string err;
+};
+
+namespace {
+
+lbpc_status fail(lbpc_handle* h, lbpc_status st, const std::string& msg) {
+  if (h)
+    h->err = msg;
+  else
+    g_err = msg;
+  return st;
+}
+
+lbpc_status hip_fail(lbpc_handle* h, hipError_t e, const char* what) {
+  return fail(h, LBPC_ERR_HIP,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(h, expr, what)                 \
+  do {                                         \
+    hipError_t e_ = (expr);                    \
+    if (e_ != hipSuccess) return hip_fail(h, e_, what); \
+  } while (0)
+
+void* at(lbpc_handle* h, size_t off) { return h->ws + off; }
+
+// step parameters for the current state (input = buffer cur)
+StepParams params_now(lbpc_handle* h) {
+  StepParams p = h->base;
+  p.fin = at(h, h->L.dist[h->cur][0]);
+  p.gin = at(h, h->L.dist[h->cur][1]);
+  p.fout = at(h, h->L.dist[1 - h->cur][0]);
+  p.gout = at(h, h->L.dist[1 - h->cur][1]);
+  p.phi = at(h, h->L.phi);
+  p.fresh = h->fresh;
+  p.phi_valid = h->phi_valid;
+  p.rho_ave = h->rho_ave;
+  return p;
+}
+
+int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return v ? std::atoi(v) : dflt;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbpc_status lbpc_workspace_bytes(const lbpc_config* cfg, size_t* bytes) {
+  const char* bad = check_config(cfg);
+  if (bad) return fail(nullptr, LBPC_ERR_ARG, bad);
+  if (!bytes) return fail(nullptr, LBPC_ERR_ARG, "bytes is NULL");
+  *bytes = plan(*cfg).total;
+  return LBPC_OK;
+}
+
+lbpc_status lbpc_create(const lbpc_config* cfg, void* dev_workspace,
+                        size_t workspace_bytes, void* hip_stream,
+                        lbpc_handle** out) {
+  if (!out) return fail(nullptr, LBPC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  const char* bad = check_config(cfg);
+  if (bad) return fail(nullptr, LBPC_ERR_ARG, bad);
+  if (cfg->flags != 0)
+    return fail(nullptr, LBPC_ERR_UNSUPPORTED,
+                "flags are test hooks of the CPU oracle only");
+  Layout L = plan(*cfg);
+  if (!dev_workspace || workspace_bytes < L.total)
+    return fail(nullptr, LBPC_ERR_OOM, "workspace missing or too small");
+  if (reinterpret_cast<uintptr_t>(dev_workspace) % ALIGN != 0)
+    return fail(nullptr, LBPC_ERR_ARG, "workspace must be 256-byte aligned");
+  lbpc_handle* h = new (std::nothrow) lbpc_handle();
+  if (!h) return fail(nullptr, LBPC_ERR_OOM, "host allocation failed");
+  h->cfg = *cfg;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  h->ws = static_cast<char*>(dev_workspace);
+  h->ws_bytes = workspace_bytes;
+  h->L = L;
+  StepParams& p = h->base;
+  std::memset(&p, 0, sizeof(p));
+  p.nx = cfg->nx;
+  p.ny = cfg->ny;
+  p.perx = cfg->bc[0] == LBPC_BC_PERIODIC;
+  p.pery = cfg->bc[2] == LBPC_BC_PERIODIC;
+  for (int i = 0; i < 4; ++i) {
+    p.bc[i] = cfg->bc[i];
+    p.T_bc[i] = cfg->T_bc[i];
+  }
+  p.W = lbpc::BLOCK - 2 * lbpc::HALO;
+  p.nbx = (cfg->nx + p.W - 1) / p.W;
+  {
+    // rows per block: enough blocks to fill 256 CUs twice over, at least
+    // 16 rows so the 4-row warm-up stays small
+    int h_rows = env_int("LBPC_TILE_H", 0);
+    if (h_rows <= 0) {
+      long long want = 2048 / p.nbx;
+      if (want < 1) want = 1;
+      h_rows = (int)((cfg->ny + want - 1) / want);
+      if (h_rows < 16) h_rows = 16;
+      if (h_rows > 256) h_rows = 256;
+    }
+    p.H = h_rows;
+  }
+  p.hot_x0 = cfg->hot_x0;
+  p.hot_x1 = cfg->hot_x1;
+  p.T_hot = cfg->T_hot;
+  p.a = cfg->a;
+  p.b = cfg->b;
+  p.R = cfg->R;
+  p.Tc = pr_Tc(*cfg);
+  p.kappa = pr_kappa(cfg->omega);
+  p.G = cfg->G;
+  p.sigma = cfg->sigma;
+  p.gx = cfg->gx;
+  p.gy = cfg->gy;
+  for (int i = 0; i < 9; ++i) {
+    p.s_f[i] = cfg->s_f[i];
+    p.s_g[i] = cfg->s_g[i];
+  }
+  p.cv = cfg->cv;
+  p.lambda0 = cfg->lambda0;
+  p.chi = cfg->chi;
+  p.k_th = (1.0 / cfg->s_g[3] - 0.5) * (1.0 / 3.0);  // Eq. (A13), c_s^2 = 1/3
+  p.lambda_mode = cfg->lambda_mode;
+  p.improved = cfg->thermal_model == LBPC_THERMAL_IMPROVED;
+  p.rho_ref = cfg->rho_ref;
+  p.T_ref = cfg->T_ref;
+  p.N = (long long)cfg->nx * cfg->ny;
+  *out = h;
+  return LBPC_OK;
+}
+
+lbpc_status lbpc_init_fields(lbpc_handle* h, const double* rho,
+                             const double* ux, const double* uy,
+                             const double* T) {
+  if (!h) return fail(nullptr, LBPC_ERR_ARG, "handle is NULL");
+  if (!rho || !ux || !uy || !T)
+    return fail(h, LBPC_ERR_ARG, "field pointer is NULL");
+  const lbpc_config& c = h->cfg;
+  const size_t N = (size_t)c.nx * c.ny;
+  double sum = 0.0;
+  for (size_t i = 0; i < N; ++i) {
+    if (!(rho[i] > 0.0 && rho[i] < 1.0 / c.b))
+      return fail(h, LBPC_ERR_ARG, "rho outside (0, 1/b)");
+    if (!(T[i] > 0.0) || !std::isfinite(T[i]) || !std::isfinite(ux[i]) ||
+        !std::isfinite(uy[i]))
+      return fail(h, LBPC_ERR_ARG, "T <= 0 or non-finite input");
+    if (!(host_psi2(c, rho[i], T[i]) >= 0.0))
+      return fail(h, LBPC_ERR_ARG, "psi^2 < 0 (p_EOS > rho c_s^2)");
+    sum += rho[i];
+  }
+  h->rho_ave = sum / (double)N;
+  double* scr = static_cast<double*>(at(h, h->L.scratch));
+  const double* src[4] = {rho, ux, uy, T};
+  for (int k = 0; k < 4; ++k)
+    HIP_TRY(h,
+            hipMemcpyAsync(scr + k * N, src[k], N * sizeof(double),
+                           hipMemcpyHostToDevice, h->stream),
+            "copy of the initial fields");
+  h->cur = 0;
+  StepParams p = params_now(h);
+  HIP_TRY(h, lbpc::launch_init(p, c.precision, scr, h->stream), "init kernel");
+  HIP_TRY(h, hipStreamSynchronize(h->stream), "init synchronise");
+  h->fresh = 1;
+  h->phi_valid = 0;
+  h->step = 0;
+  h->initialised = 1;
+  return LBPC_OK;
+}
+
+lbpc_status lbpc_step(lbpc_handle* h, int64_t n) {
+  if (!h) return fail(nullptr, LBPC_ERR_ARG, "handle is NULL");
+  if (n < 0) return fail(h, LBPC_ERR_ARG, "n < 0");
+  if (!h->initialised) return fail(h, LBPC_ERR_STATE, "step before init");
+  for (int64_t s = 0; s < n; ++s) {
+    StepParams p = params_now(h);
+    HIP_TRY(h, lbpc::launch_step(p, h->cfg.precision, h->stream),
+            "step kernel");
+    h->cur = 1 - h->cur;
+    h->fresh = 0;
+    h->phi_valid = 1;
+    h->step += 1;
+  }
+  return LBPC_OK;
+}
+
+lbpc_status lbpc_get_rho_u_T(lbpc_handle* h, double* rho, double* ux,
+                             double* uy, double* T) {
+  if (!h) return fail(nullptr, LBPC_ERR_ARG, "handle is NULL");
+  if (!h->initialised) return fail(h, LBPC_ERR_STATE, "get before init");
+  const size_t N = (size_t)h->cfg.nx * h->cfg.ny;
+  double* scr = static_cast<double*>(at(h, h->L.scratch));
+  StepParams p = params_now(h);
+  HIP_TRY(h, lbpc::launch_macro(p, h->cfg.precision, scr, h->stream),
+          "macro kernels");
+  double* dst[4] = {rho, ux, uy, T};
+  const int slot[4] = {0, 1, 2, 3};
+  for (int k = 0; k < 4; ++k)
+    if (dst[k])
+      HIP_TRY(h,
+              hipMemcpyAsync(dst[k], scr + slot[k] * N, N * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream),
+              "copy of the fields");
+  HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+  for (int k = 0; k < 4; ++k)
+    if (dst[k])
+      for (size_t i = 0; i < N; ++i)
+        if (!std::isfinite(dst[k][i]))
+          return fail(h, LBPC_ERR_NUMERIC, "non-finite field value");
+  return LBPC_OK;
+}
+
+lbpc_status lbpc_get_diag(lbpc_handle* h, lbpc_diag* out) {
+  if (!h) return fail(nullptr, LBPC_ERR_ARG, "handle is NULL");
+  if (!out) return fail(h, LBPC_ERR_ARG, "out is NULL");
+  if (!h->initialised) return fail(h, LBPC_ERR_STATE, "diag before init");
+  double* scr = static_cast<double*>(at(h, h->L.scratch));
+  StepParams p = params_now(h);
+  HIP_TRY(h, lbpc::launch_macro(p, h->cfg.precision, scr, h->stream),
+          "macro kernels");
+  double* dout = static_cast<double*>(at(h, h->L.diag_out));
+  HIP_TRY(h,
+          lbpc::launch_diag(p, scr, h->cfg.rho_v, h->cfg.rho_l,
+                            static_cast<double*>(at(h, h->L.partial)), dout,
+                            h->stream),
+          "diagnostic kernels");
+  double r[8];
+  HIP_TRY(h,
+          hipMemcpyAsync(r, dout, sizeof(r), hipMemcpyDeviceToHost,
+                         h->stream),
+          "copy of the diagnostics");
+  HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+  std::memset(out, 0, sizeof(*out));
+  out->mass = r[0];
+  out->sum_T = r[1];
+  out->sum_rhocvT = r[2];
+  out->liquid_area = r[3];
+  out->radius = std::sqrt(r[3] / M_PI);
+  out->radius_count = std::sqrt(r[4] / M_PI);
+  out->max_speed = r[5];
+  out->nonfinite = r[6] != 0.0 || !std::isfinite(r[0]) || !std::isfinite(r[1]);
+  out->step = h->step;
+  return LBPC_OK;
+}
+
+lbpc_status lbpc_state_bytes(const lbpc_handle* h, size_t* bytes) {
+  if (!h || !bytes) return fail(nullptr, LBPC_ERR_ARG, "NULL argument");
+  const size_t N = (size_t)h->cfg.nx * h->cfg.ny;
+  *bytes = 19 * N * sizeof(double) + 3 * sizeof(int64_t);
+  return LBPC_OK;
+}
+
+lbpc_status lbpc_save_state(lbpc_handle* h, void* host, size_t bytes) {
+  if (!h) return fail(nullptr, LBPC_ERR_ARG, "handle is NULL");
+  if (!h->initialised) return fail(h, LBPC_ERR_STATE, "save before init");
+  size_t need;
+  lbpc_state_bytes(h, &need);
+  if (!host || bytes < need) return fail(h, LBPC_ERR_ARG, "buffer too small");
+  const size_t N = (size_t)h->cfg.nx * h->cfg.ny;
+  double* scr = static_cast<double*>(at(h, h->L.scratch));
+  double* dst = static_cast<double*>(host);
+  StepParams p = params_now(h);
+  for (int which = 0; which < 18; ++which) {
+    HIP_TRY(h, lbpc::launch_canon(p, h->cfg.precision, which, scr, h->stream),
+            "canonical-state kernel");
+    HIP_TRY(h,
+            hipMemcpyAsync(dst + which * N, scr, N * sizeof(double),
+                           hipMemcpyDeviceToHost, h->stream),
+            "state copy");
+    HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+  }
+  HIP_TRY(h, lbpc::launch_phi_out(p, h->cfg.precision, scr, h->stream),
+          "phi copy kernel");
+  HIP_TRY(h,
+          hipMemcpyAsync(dst + 18 * N, scr, N * sizeof(double),
+                         hipMemcpyDeviceToHost, h->stream),
+          "state copy");
+  HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+  int64_t meta[3];
+  meta[0] = h->phi_valid;
+  std::memcpy(&meta[1], &h->rho_ave, sizeof(double));
+  meta[2] = h->step;
+  std::memcpy(dst + 19 * N, meta, sizeof(meta));
+  return LBPC_OK;
+}
+
+lbpc_status lbpc_load_state(lbpc_handle* h, const void* host, size_t bytes) {
+  if (!h) return fail(nullptr, LBPC_ERR_ARG, "handle is NULL");
+  size_t need;
+  lbpc_state_bytes(h, &need);
+  if (!host || bytes < need) return fail(h, LBPC_ERR_ARG, "buffer too small");
+  const size_t N = (size_t)h->cfg.nx * h->cfg.ny;
+  double* scr = static_cast<double*>(at(h, h->L.scratch));
+  const double* src = static_cast<const double*>(host);
+  h->cur = 0;
+  StepParams p = params_now(h);
+  for (int which = 0; which < 18; ++which) {
+    HIP_TRY(h,
+            hipMemcpyAsync(scr, src + which * N, N * sizeof(double),
+                           hipMemcpyHostToDevice, h->stream),
+            "state copy");
+    HIP_TRY(h, lbpc::launch_load(p, h->cfg.precision, which, scr, h->stream),
+            "state load kernel");
+    HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+  }
+  HIP_TRY(h,
+          hipMemcpyAsync(scr, src + 18 * N, N * sizeof(double),
+                         hipMemcpyHostToDevice, h->stream),
+          "state copy");
+  HIP_TRY(h, lbpc::launch_phi_in(p, h->cfg.precision, scr, h->stream),
+          "phi load kernel");
+  HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+  int64_t meta[3];
+  std::memcpy(meta, src + 19 * N, sizeof(meta));
+  h->phi_valid = meta[0] != 0;
+  std::memcpy(&h->rho_ave, &meta[1], sizeof(double));
+  h->step = meta[2];
+  h->fresh = 1;
+  h->initialised = 1;
+  return LBPC_OK;
+}
+
+void lbpc_destroy(lbpc_handle* h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+}
+
+const char* lbpc_last_error(const lbpc_handle* h) {
+  return h ? h->err.c_str() : g_err.c_str();
+}
+
+}  // extern "C"

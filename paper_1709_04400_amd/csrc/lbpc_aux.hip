@@ -1,0 +1,324 @@
+// lbpc_aux.hip -- the kernels around the fused step: initial equilibria,
+// macroscopic fields at the current time level (rho, v, T), FP64
+// diagnostic reductions and the canonical-state transfers of
+// checkpoint / restart.  None of these is on the per-step path.
+#include "lbpc_device.h"
+
+namespace lbpc {
+
+constexpr int AUX_BLOCK = 256;
+
+// f = M^-1 m^eq(rho, u) of the flow model, g = M^-1 m^eq(T, u) of Eq. (53);
+// the host FP64 fields sit in `in` as [rho | ux | uy | T], each of N values.
+template <int P>
+__global__ __launch_bounds__(AUX_BLOCK) void k_init(StepParams p,
+                                                    const double* in) {
+  using Tr = Prec<P>;
+  using S = typename Tr::S;
+  const long long N = p.N;
+  const long long i = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
+  if (i >= N) return;
+  const double rho = in[i], vx = in[N + i], vy = in[2 * N + i],
+               T = in[3 * N + i];
+  const double v2 = vx * vx + vy * vy;
+  double m[Q], f[Q];
+  m[0] = rho;
+  m[1] = rho * (-2.0 + 3.0 * v2);
+  m[2] = rho * (1.0 - 3.0 * v2);
+  m[3] = rho * vx;
+  m[4] = -rho * vx;
+  m[5] = rho * vy;
+  m[6] = -rho * vy;
+  m[7] = rho * (vx * vx - vy * vy);
+  m[8] = rho * vx * vy;
+  from_moments(m, f);
+  S* fo = static_cast<S*>(const_cast<void*>(p.fin));
+  S* go = static_cast<S*>(const_cast<void*>(p.gin));
+#pragma unroll
+  for (int a = 0; a < Q; ++a)
+    Tr::st(fo, a * N + i,
+           typename Tr::C(f[a] - (Tr::shift ? w_lat(a) * p.rho_ref : 0.0)));
+  m[0] = T;
+  m[1] = -2.0 * T;
+  m[2] = 2.0 * T;
+  m[3] = T * vx;
+  m[4] = -T * vx;
+  m[5] = T * vy;
+  m[6] = -T * vy;
+  m[7] = 0.0;
+  m[8] = 0.0;
+  from_moments(m, f);
+#pragma unroll
+  for (int a = 0; a < Q; ++a)
+    Tr::st(go, a * N + i,
+           typename Tr::C(f[a] - (Tr::shift ? w_rest(a) * p.T_ref : 0.0)));
+}
+
+// moments at the current time level: out = [rho | jx | jy | T | psi], FP64
+template <int P, bool GEN>
+__global__ __launch_bounds__(AUX_BLOCK) void k_macro1(StepParams p,
+                                                      double* out) {
+  using Tr = Prec<P>;
+  using C = typename Tr::C;
+  const long long N = p.N;
+  const long long i = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
+  if (i >= N) return;
+  const int x = (int)(i % p.nx), y = (int)(i / p.nx);
+  C fsh[Q], gsh[Q], fn[Q], gn[Q];
+  storage_shifts<P>(p, fsh, gsh);
+  pull_node<P, GEN>(p, static_cast<const typename Tr::S*>(p.fin),
+                    static_cast<const typename Tr::S*>(p.gin), x, y, fsh, gsh,
+                    fn, gn);
+  C m[Q];
+  to_moments(fn, m);
+  const C T = gn[0] + (gn[1] + gn[2] + gn[3] + gn[4]) +
+              (gn[5] + gn[6] + gn[7] + gn[8]);
+  out[i] = (double)m[0];
+  out[N + i] = (double)m[3];
+  out[2 * N + i] = (double)m[5];
+  out[3 * N + i] = (double)T;
+  out[4 * N + i] = pseudo_psi(p, (double)m[0], (double)T);
+}
+
+// force and velocity v = (j + F/2)/rho; overwrites jx, jy with vx, vy
+__global__ __launch_bounds__(AUX_BLOCK) void k_macro2(StepParams p,
+                                                      double* io) {
+  const long long N = p.N;
+  const long long i = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
+  if (i >= N) return;
+  const int x = (int)(i % p.nx), y = (int)(i / p.nx);
+  const double* psi = io + 4 * N;
+  double sx = 0.0, sy = 0.0;
+  const int DX[8] = {1, 0, -1, 0, 1, -1, -1, 1};
+  const int DY[8] = {0, 1, 0, -1, 1, 1, -1, -1};
+  for (int k = 0; k < 8; ++k) {
+    Ghost gh = resolve(p, x + DX[k], y + DY[k]);
+    const double w = k < 4 ? 1.0 / 3.0 : 1.0 / 12.0;
+    const double pn = psi[(long long)gh.y * p.nx + gh.x];
+    sx += w * pn * DX[k];
+    sy += w * pn * DY[k];
+  }
+  const double rho = io[i];
+  double Fx = -p.G * psi[i] * sx + (rho - p.rho_ave) * p.gx;
+  double Fy = -p.G * psi[i] * sy + (rho - p.rho_ave) * p.gy;
+  io[N + i] = (io[N + i] + 0.5 * Fx) / rho;
+  io[2 * N + i] = (io[2 * N + i] + 0.5 * Fy) / rho;
+}
+
+// FP64 sums over the macro fields: per block partials [block][8] =
+// {sum rho, sum T, sum rho cv T, liquid area, count, max |v|, nonfinite, 0}
+__global__ __launch_bounds__(AUX_BLOCK) void k_diag_partial(
+    StepParams p, const double* io, double rho_v, double rho_l,
+    double* partial) {
+  __shared__ double red[8][AUX_BLOCK];
+  const long long N = p.N;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (long long i = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x; i < N;
+       i += (long long)gridDim.x * AUX_BLOCK) {
+    const double rho = io[i], vx = io[N + i], vy = io[2 * N + i],
+                 T = io[3 * N + i];
+    acc[0] += rho;
+    acc[1] += T;
+    acc[2] += rho * p.cv * T;
+    double fr = (rho - rho_v) / (rho_l - rho_v);
+    fr = fr < 0.0 ? 0.0 : (fr > 1.0 ? 1.0 : fr);
+    acc[3] += fr;
+    acc[4] += rho > 0.5 * (rho_l + rho_v) ? 1.0 : 0.0;
+    const double sp = sqrt(vx * vx + vy * vy);
+    acc[5] = sp > acc[5] ? sp : acc[5];
+    if (!isfinite(rho) || !isfinite(T) || !isfinite(vx) || !isfinite(vy))
+      acc[6] = 1.0;
+  }
+  for (int k = 0; k < 8; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = AUX_BLOCK / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      for (int k = 0; k < 8; ++k) {
+        const double o = red[k][threadIdx.x + s];
+        if (k == 5 || k == 6)
+          red[k][threadIdx.x] = o > red[k][threadIdx.x] ? o : red[k][threadIdx.x];
+        else
+          red[k][threadIdx.x] += o;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 8) partial[blockIdx.x * 8 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// fixed-order final sum of the partials (one thread, deterministic)
+__global__ void k_diag_final(const double* partial, int nblk, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = 0; b < nblk; ++b)
+    for (int k = 0; k < 8; ++k) {
+      const double v = partial[b * 8 + k];
+      if (k == 5 || k == 6)
+        acc[k] = v > acc[k] ? v : acc[k];
+      else
+        acc[k] += v;
+    }
+  for (int k = 0; k < 8; ++k) out[k] = acc[k];
+}
+
+// canonical FP64 f(t) (which = 0..8) or g(t) (which = 9..17), one direction
+template <int P, bool GEN>
+__global__ __launch_bounds__(AUX_BLOCK) void k_canon(StepParams p, int which,
+                                                     double* out) {
+  using Tr = Prec<P>;
+  using C = typename Tr::C;
+  const long long N = p.N;
+  const long long i = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
+  if (i >= N) return;
+  const int x = (int)(i % p.nx), y = (int)(i / p.nx);
+  C fsh[Q], gsh[Q], fn[Q], gn[Q];
+  storage_shifts<P>(p, fsh, gsh);
+  pull_node<P, GEN>(p, static_cast<const typename Tr::S*>(p.fin),
+                    static_cast<const typename Tr::S*>(p.gin), x, y, fsh, gsh,
+                    fn, gn);
+  C v = C(0);
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    if (which == a) v = fn[a];
+    if (which == Q + a) v = gn[a];
+  }
+  out[i] = (double)v;
+}
+
+// FP64 canonical direction `which` -> storage buffer (fresh layout)
+template <int P>
+__global__ __launch_bounds__(AUX_BLOCK) void k_load(StepParams p, int which,
+                                                    const double* in) {
+  using Tr = Prec<P>;
+  using S = typename Tr::S;
+  const long long N = p.N;
+  const long long i = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
+  if (i >= N) return;
+  const int a = which % Q;
+  if (which < Q) {
+    S* fo = static_cast<S*>(const_cast<void*>(p.fin));
+    Tr::st(fo, a * N + i,
+           typename Tr::C(in[i] - (Tr::shift ? w_lat(a) * p.rho_ref : 0.0)));
+  } else {
+    S* go = static_cast<S*>(const_cast<void*>(p.gin));
+    Tr::st(go, a * N + i,
+           typename Tr::C(in[i] - (Tr::shift ? w_rest(a) * p.T_ref : 0.0)));
+  }
+}
+
+// phi history between its compute precision and FP64
+template <class C>
+__global__ __launch_bounds__(AUX_BLOCK) void k_phi_out(long long N,
+                                                       const C* phi,
+                                                       double* out) {
+  const long long i = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
+  if (i < N) out[i] = (double)phi[i];
+}
+template <class C>
+__global__ __launch_bounds__(AUX_BLOCK) void k_phi_in(long long N, C* phi,
+                                                      const double* in) {
+  const long long i = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
+  if (i < N) phi[i] = C(in[i]);
+}
+
+// ------------------------------------------------------------- launchers
+
+static inline unsigned nblocks(long long N) {
+  return (unsigned)((N + AUX_BLOCK - 1) / AUX_BLOCK);
+}
+
+#define LBPC_PREC_SWITCH(prec, X) \
+  switch (prec) {                 \
+    case 0: X(0); break;          \
+    case 1: X(1); break;          \
+    case 2: X(2); break;          \
+    case 3: X(3); break;          \
+    default: return hipErrorInvalidValue; \
+  }
+
+hipError_t launch_init(const StepParams& p, int prec, const double* in,
+                       hipStream_t s) {
+#define X(PR) hipLaunchKernelGGL(k_init<PR>, dim3(nblocks(p.N)), dim3(AUX_BLOCK), 0, s, p, in)
+  LBPC_PREC_SWITCH(prec, X)
+#undef X
+  return hipGetLastError();
+}
+
+hipError_t launch_macro(const StepParams& p, int prec, double* io,
+                        hipStream_t s) {
+  const bool gen = !(p.perx && p.pery);
+#define X(PR)                                                                    \
+  if (gen)                                                                       \
+    hipLaunchKernelGGL((k_macro1<PR, true>), dim3(nblocks(p.N)), dim3(AUX_BLOCK), 0, s, p, io); \
+  else                                                                           \
+    hipLaunchKernelGGL((k_macro1<PR, false>), dim3(nblocks(p.N)), dim3(AUX_BLOCK), 0, s, p, io);
+  LBPC_PREC_SWITCH(prec, X)
+#undef X
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_macro2, dim3(nblocks(p.N)), dim3(AUX_BLOCK), 0, s, p,
+                     io);
+  return hipGetLastError();
+}
+
+int diag_blocks(long long N) {
+  long long b = (N + AUX_BLOCK - 1) / AUX_BLOCK;
+  return (int)(b < 1024 ? b : 1024);
+}
+
+hipError_t launch_diag(const StepParams& p, const double* io, double rho_v,
+                       double rho_l, double* partial, double* out,
+                       hipStream_t s) {
+  const int nb = diag_blocks(p.N);
+  hipLaunchKernelGGL(k_diag_partial, dim3(nb), dim3(AUX_BLOCK), 0, s, p, io,
+                     rho_v, rho_l, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, partial, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_canon(const StepParams& p, int prec, int which, double* out,
+                        hipStream_t s) {
+  const bool gen = !(p.perx && p.pery);
+#define X(PR)                                                                    \
+  if (gen)                                                                       \
+    hipLaunchKernelGGL((k_canon<PR, true>), dim3(nblocks(p.N)), dim3(AUX_BLOCK), 0, s, p, which, out); \
+  else                                                                           \
+    hipLaunchKernelGGL((k_canon<PR, false>), dim3(nblocks(p.N)), dim3(AUX_BLOCK), 0, s, p, which, out);
+  LBPC_PREC_SWITCH(prec, X)
+#undef X
+  return hipGetLastError();
+}
+
+hipError_t launch_load(const StepParams& p, int prec, int which,
+                       const double* in, hipStream_t s) {
+#define X(PR) hipLaunchKernelGGL(k_load<PR>, dim3(nblocks(p.N)), dim3(AUX_BLOCK), 0, s, p, which, in)
+  LBPC_PREC_SWITCH(prec, X)
+#undef X
+  return hipGetLastError();
+}
+
+hipError_t launch_phi_out(const StepParams& p, int prec, double* out,
+                          hipStream_t s) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_phi_out<double>, dim3(nblocks(p.N)), dim3(AUX_BLOCK),
+                       0, s, p.N, static_cast<const double*>(p.phi), out);
+  else
+    hipLaunchKernelGGL(k_phi_out<float>, dim3(nblocks(p.N)), dim3(AUX_BLOCK),
+                       0, s, p.N, static_cast<const float*>(p.phi), out);
+  return hipGetLastError();
+}
+
+hipError_t launch_phi_in(const StepParams& p, int prec, const double* in,
+                         hipStream_t s) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_phi_in<double>, dim3(nblocks(p.N)), dim3(AUX_BLOCK),
+                       0, s, p.N, static_cast<double*>(p.phi), in);
+  else
+    hipLaunchKernelGGL(k_phi_in<float>, dim3(nblocks(p.N)), dim3(AUX_BLOCK),
+                       0, s, p.N, static_cast<float*>(p.phi), in);
+  return hipGetLastError();
+}
+
+}  // namespace lbpc

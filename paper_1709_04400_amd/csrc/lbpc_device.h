@@ -1,0 +1,298 @@
+// lbpc_device.h -- device-side building blocks of the gfx950 step kernels:
+// kernel parameters, storage-precision traits, the Peng-Robinson EOS of
+// Eq. (56), the ghost rule of the non-periodic sides and the MRT transforms.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbpc {
+
+constexpr int Q = 9;
+constexpr int BLOCK = 256;      // threads per block of the fused step kernel
+constexpr int HALO = 2;         // columns of halo on each side of a strip
+constexpr int RING = 5;         // rows held in the LDS ring buffers
+
+enum { BC_PERIODIC = 0, BC_WALL = 1, BC_OPEN = 2 };
+enum { GH_INSIDE = 0, GH_WALL = 1, GH_OPEN = 2 };
+
+// Everything a step kernel needs, passed by value.
+struct StepParams {
+  // lattice and tiling
+  int nx, ny;
+  int perx, pery;          // 1 if that axis is periodic
+  int bc[4];               // side kinds x-, x+, y-, y+
+  int W, H;                // interior columns / rows per block
+  int nbx;                 // blocks along x
+  int hot_x0, hot_x1;
+  double T_bc[4], T_hot;
+  // EOS (Eq. 56) and flow model
+  double a, b, R, Tc, kappa;
+  double G, sigma;
+  double gx, gy, rho_ave;
+  double s_f[9];
+  // thermal model
+  double s_g[9];
+  double cv, lambda0, chi, k_th;
+  int lambda_mode, improved;
+  // storage shift (rho_ref, T_ref of the shifted forms)
+  double rho_ref, T_ref;
+  // state flags
+  int fresh;      // 1: the input buffer holds pre-collision f(t) (no pull)
+  int phi_valid;  // 0: first step, phi_prev := phi
+  // buffers
+  const void* fin;  // [9][N] input f (post-collision f*(t-1) or fresh f(t))
+  const void* gin;
+  void* fout;       // [9][N] output f*(t)
+  void* gout;
+  void* phi;        // [N] phi(t-1) in, phi(t) out (compute precision)
+  long long N;      // nx * ny
+};
+
+// ------------------------------------------------------- precision traits
+
+template <int P> struct Prec;
+template <> struct Prec<0> {  // FP64 storage and arithmetic
+  using S = double;
+  using C = double;
+  static constexpr bool shift = false;
+  __device__ static C ld(const S* p, long long i) { return p[i]; }
+  __device__ static void st(S* p, long long i, C v) { p[i] = v; }
+};
+template <> struct Prec<1> {  // FP32 storage and arithmetic
+  using S = float;
+  using C = float;
+  static constexpr bool shift = false;
+  __device__ static C ld(const S* p, long long i) { return p[i]; }
+  __device__ static void st(S* p, long long i, C v) { p[i] = v; }
+};
+template <> struct Prec<2> {  // FP32 deviations from the rest equilibrium
+  using S = float;
+  using C = float;
+  static constexpr bool shift = true;
+  __device__ static C ld(const S* p, long long i) { return p[i]; }
+  __device__ static void st(S* p, long long i, C v) { p[i] = v; }
+};
+template <> struct Prec<3> {  // FP16 deviations, FP32 arithmetic
+  using S = __half;
+  using C = float;
+  static constexpr bool shift = true;
+  __device__ static C ld(const S* p, long long i) { return __half2float(p[i]); }
+  __device__ static void st(S* p, long long i, C v) { p[i] = __float2half_rn(v); }
+};
+
+// D2Q9 weights (shift of f) and rest weights of Eq. (53) (shift of g)
+__device__ __forceinline__ double w_lat(int a) {
+  return a == 0 ? 4.0 / 9.0 : (a < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+__device__ __forceinline__ double w_rest(int a) {
+  return a == 0 ? 5.0 / 9.0 : 1.0 / 18.0;
+}
+
+// ---------------------------------------------------------- EOS, Eq. (56)
+
+__device__ __forceinline__ double pr_p(const StepParams& p, double rho,
+                                       double T) {
+  double s = 1.0 + p.kappa * (1.0 - sqrt(T / p.Tc));
+  double th = s * s;
+  return rho * p.R * T / (1.0 - p.b * rho) -
+         p.a * th * rho * rho / (1.0 + 2.0 * p.b * rho - p.b * p.b * rho * rho);
+}
+
+__device__ __forceinline__ double pr_dpdT(const StepParams& p, double rho,
+                                          double T) {
+  double s = 1.0 + p.kappa * (1.0 - sqrt(T / p.Tc));
+  double dth = 2.0 * s * (-p.kappa) * (0.5 / sqrt(T * p.Tc));
+  return rho * p.R / (1.0 - p.b * rho) -
+         p.a * dth * rho * rho /
+             (1.0 + 2.0 * p.b * rho - p.b * p.b * rho * rho);
+}
+
+// psi = sqrt(2 (p_EOS - rho c_s^2) / G) with c = 1, evaluated in FP64 (the
+// difference cancels strongly in the liquid)
+__device__ __forceinline__ double pseudo_psi(const StepParams& p, double rho,
+                                             double T) {
+  double psi2 = 2.0 * (pr_p(p, rho, T) - rho * (1.0 / 3.0)) / p.G;
+  return sqrt(psi2 > 0.0 ? psi2 : 0.0);
+}
+
+// ------------------------------------------------------------ ghost rule
+
+__device__ __forceinline__ double side_T(const StepParams& p, int side,
+                                         int col) {
+  if (side == 2 && col >= p.hot_x0 && col < p.hot_x1) return p.T_hot;
+  return p.T_bc[side];
+}
+
+struct Ghost {
+  int kind;    // GH_INSIDE, GH_WALL, GH_OPEN
+  int x, y;    // node after periodic wrap (inside) or clamping (ghost)
+  double T;    // ghost temperature
+};
+
+// Resolve an unwrapped lattice position: wrap periodic axes, clamp the
+// others, and classify (a wall wins over an open side; the y side gives T at
+// corners).
+__device__ __forceinline__ Ghost resolve(const StepParams& p, int x, int y) {
+  Ghost g;
+  int xs = -1, ys = -1;
+  if (x < 0 || x >= p.nx) {
+    int side = x < 0 ? 0 : 1;
+    if (p.perx) {
+      x = x < 0 ? x + p.nx : x - p.nx;
+    } else {
+      xs = side;
+      x = x < 0 ? 0 : p.nx - 1;
+    }
+  }
+  if (y < 0 || y >= p.ny) {
+    int side = y < 0 ? 2 : 3;
+    if (p.pery) {
+      y = y < 0 ? y + p.ny : y - p.ny;
+    } else {
+      ys = side;
+      y = y < 0 ? 0 : p.ny - 1;
+    }
+  }
+  g.x = x;
+  g.y = y;
+  g.T = 0.0;
+  if (xs < 0 && ys < 0) {
+    g.kind = GH_INSIDE;
+  } else {
+    bool wall = (ys >= 0 && p.bc[ys] == BC_WALL) ||
+                (xs >= 0 && p.bc[xs] == BC_WALL);
+    g.kind = wall ? GH_WALL : GH_OPEN;
+    g.T = ys >= 0 ? side_T(p, ys, x) : side_T(p, xs, x);
+  }
+  return g;
+}
+
+// ------------------------------------------------------------- the pull
+// f_a(x, t) = f*_a(x - e_a, t - 1), and likewise g, at lattice node (x, y),
+// with the side rules at edge nodes: across a wall halfway bounce-back for f
+// and anti-bounce-back g_a = -g*_abar + 2 wg_a T_wall for g; across an open
+// side f_a = f*_a(clamped source), g_a = wg_a T_side.  With p.fresh the
+// buffers hold f(t), g(t) themselves and are read in place.  Values are
+// returned unshifted, in compute precision.
+template <int P, bool GEN>
+__device__ __forceinline__ void pull_node(
+    const StepParams& p, const typename Prec<P>::S* __restrict__ fin,
+    const typename Prec<P>::S* __restrict__ gin, int x, int y,
+    const typename Prec<P>::C fsh[Q], const typename Prec<P>::C gsh[Q],
+    typename Prec<P>::C fn[Q], typename Prec<P>::C gn[Q]) {
+  using Tr = Prec<P>;
+  using C = typename Tr::C;
+  const int nx = p.nx, ny = p.ny;
+  const long long N = p.N;
+  const long long row = (long long)y * nx;
+  if (p.fresh) {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      fn[a] = Tr::ld(fin, a * N + row + x) + fsh[a];
+      gn[a] = Tr::ld(gin, a * N + row + x) + gsh[a];
+    }
+    return;
+  }
+  const bool edge = GEN && ((!p.perx && (x == 0 || x == nx - 1)) ||
+                            (!p.pery && (y == 0 || y == ny - 1)));
+  if (!edge) {
+    int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
+    if (xm < 0) xm += nx;
+    if (xp >= nx) xp -= nx;
+    if (ym < 0) ym += ny;
+    if (yp >= ny) yp -= ny;
+    const long long rm = (long long)ym * nx, rp = (long long)yp * nx;
+    // source of direction a is x - e_a
+    const long long src[Q] = {row + x,  row + xm, rm + x,  row + xp, rp + x,
+                              rm + xm, rm + xp,  rp + xp, rp + xm};
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      fn[a] = Tr::ld(fin, a * N + src[a]) + fsh[a];
+      gn[a] = Tr::ld(gin, a * N + src[a]) + gsh[a];
+    }
+    return;
+  }
+  constexpr int EXs[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  constexpr int EYs[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  constexpr int OPs[Q] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+  const long long self = row + x;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    Ghost gh = resolve(p, x - EXs[a], y - EYs[a]);
+    if (gh.kind == GH_INSIDE) {
+      const long long s = (long long)gh.y * nx + gh.x;
+      fn[a] = Tr::ld(fin, a * N + s) + fsh[a];
+      gn[a] = Tr::ld(gin, a * N + s) + gsh[a];
+    } else if (gh.kind == GH_WALL) {
+      const int o = OPs[a];
+      fn[a] = Tr::ld(fin, o * N + self) + fsh[o];
+      gn[a] = -(Tr::ld(gin, o * N + self) + gsh[o]) +
+              C(2.0 * w_rest(a) * gh.T);
+    } else {
+      const long long s = (long long)gh.y * nx + gh.x;
+      fn[a] = Tr::ld(fin, a * N + s) + fsh[a];
+      gn[a] = C(w_rest(a) * gh.T);
+    }
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void storage_shifts(const StepParams& p,
+                                               typename Prec<P>::C fsh[Q],
+                                               typename Prec<P>::C gsh[Q]) {
+  using C = typename Prec<P>::C;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    fsh[a] = Prec<P>::shift ? C(w_lat(a) * p.rho_ref) : C(0);
+    gsh[a] = Prec<P>::shift ? C(w_rest(a) * p.T_ref) : C(0);
+  }
+}
+
+// ------------------------------------------------------- MRT transforms
+// M: rows (rho, e, eps, jx, qx, jy, qy, pxx, pxy) over the D2Q9 order
+// 0 rest, 1 +x, 2 +y, 3 -x, 4 -y, 5 (+,+), 6 (-,+), 7 (-,-), 8 (+,-).
+
+template <class C>
+__device__ __forceinline__ void to_moments(const C f[9], C m[9]) {
+  C sa = f[1] + f[2] + f[3] + f[4];
+  C sd = f[5] + f[6] + f[7] + f[8];
+  C dx1 = f[1] - f[3], dy1 = f[2] - f[4];
+  C dxd = f[5] - f[6] - f[7] + f[8];
+  C dyd = f[5] + f[6] - f[7] - f[8];
+  m[0] = f[0] + sa + sd;
+  m[1] = -C(4) * f[0] - sa + C(2) * sd;
+  m[2] = C(4) * f[0] - C(2) * sa + sd;
+  m[3] = dx1 + dxd;
+  m[4] = -C(2) * dx1 + dxd;
+  m[5] = dy1 + dyd;
+  m[6] = -C(2) * dy1 + dyd;
+  m[7] = f[1] - f[2] + f[3] - f[4];
+  m[8] = f[5] - f[6] + f[7] - f[8];
+}
+
+// f = M^-1 m with M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12,
+// 1/4, 1/4)
+template <class C>
+__device__ __forceinline__ void from_moments(const C m[9], C f[9]) {
+  C a0 = m[0] * C(1.0 / 9.0), a1 = m[1] * C(1.0 / 36.0),
+    a2 = m[2] * C(1.0 / 36.0), a3 = m[3] * C(1.0 / 6.0),
+    a4 = m[4] * C(1.0 / 12.0), a5 = m[5] * C(1.0 / 6.0),
+    a6 = m[6] * C(1.0 / 12.0), a7 = m[7] * C(0.25), a8 = m[8] * C(0.25);
+  C bax = a0 - a1 - C(2) * a2;   // axis directions
+  C bdg = a0 + C(2) * a1 + a2;   // diagonal directions
+  C px = a3 - C(2) * a4, py = a5 - C(2) * a6;
+  C qx = a3 + a4, qy = a5 + a6;
+  f[0] = a0 - C(4) * a1 + C(4) * a2;
+  f[1] = bax + px + a7;
+  f[3] = bax - px + a7;
+  f[2] = bax + py - a7;
+  f[4] = bax - py - a7;
+  f[5] = bdg + qx + qy + a8;
+  f[6] = bdg - qx + qy - a8;
+  f[7] = bdg - qx - qy + a8;
+  f[8] = bdg + qx - qy - a8;
+}
+
+}  // namespace lbpc

@@ -1,0 +1,237 @@
+"""ctypes binding of liblbpc.so (include/lbpc.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of the library.  PyTorch supplies the device workspace and the HIP stream.
+The module-level functions carry the C names; :class:`Simulation` bundles one
+handle with its workspace.  Loading fails loudly when the library is absent.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbpc.so")
+
+OK, ERR_ARG, ERR_HIP, ERR_OOM, ERR_STATE, ERR_NUMERIC, ERR_UNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6)
+FP64, FP32, FP32_SHIFTED, FP16_SHIFTED = 0, 1, 2, 3
+
+# every entry point declared in include/lbpc.h
+EXPORTS = (
+    "lbpc_workspace_bytes", "lbpc_create", "lbpc_init_fields", "lbpc_step",
+    "lbpc_get_rho_u_T", "lbpc_get_diag", "lbpc_state_bytes",
+    "lbpc_save_state", "lbpc_load_state", "lbpc_destroy", "lbpc_last_error",
+)
+
+
+class Config(ctypes.Structure):
+    """Mirror of ``lbpc_config``."""
+    _fields_ = [
+        ("a", ctypes.c_double), ("b", ctypes.c_double),
+        ("R", ctypes.c_double), ("omega", ctypes.c_double),
+        ("cv", ctypes.c_double), ("lambda0", ctypes.c_double),
+        ("chi", ctypes.c_double),
+        ("s_f", ctypes.c_double * 9), ("s_g", ctypes.c_double * 9),
+        ("G", ctypes.c_double), ("sigma", ctypes.c_double),
+        ("gx", ctypes.c_double), ("gy", ctypes.c_double),
+        ("T_bc", ctypes.c_double * 4), ("T_hot", ctypes.c_double),
+        ("rho_ref", ctypes.c_double), ("T_ref", ctypes.c_double),
+        ("rho_v", ctypes.c_double), ("rho_l", ctypes.c_double),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("bc", ctypes.c_int32 * 4),
+        ("hot_x0", ctypes.c_int32), ("hot_x1", ctypes.c_int32),
+        ("lambda_mode", ctypes.c_int32), ("thermal_model", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
+    ]
+
+
+class Diag(ctypes.Structure):
+    """Mirror of ``lbpc_diag``."""
+    _fields_ = [
+        ("mass", ctypes.c_double), ("sum_T", ctypes.c_double),
+        ("sum_rhocvT", ctypes.c_double), ("liquid_area", ctypes.c_double),
+        ("radius", ctypes.c_double), ("radius_count", ctypes.c_double),
+        ("max_speed", ctypes.c_double), ("sum_S0", ctypes.c_double),
+        ("sum_Fx", ctypes.c_double), ("sum_Fy", ctypes.c_double),
+        ("step", ctypes.c_int64), ("nonfinite", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+    ]
+
+
+class LbpcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"lbpc status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+        L.lbpc_workspace_bytes.argtypes = [ctypes.POINTER(Config),
+                                           ctypes.POINTER(ctypes.c_size_t)]
+        L.lbpc_create.argtypes = [ctypes.POINTER(Config), vp, ctypes.c_size_t,
+                                  vp, ctypes.POINTER(vp)]
+        L.lbpc_init_fields.argtypes = [vp, dp, dp, dp, dp]
+        L.lbpc_step.argtypes = [vp, ctypes.c_int64]
+        L.lbpc_get_rho_u_T.argtypes = [vp, dp, dp, dp, dp]
+        L.lbpc_get_diag.argtypes = [vp, ctypes.POINTER(Diag)]
+        L.lbpc_state_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.lbpc_save_state.argtypes = [vp, vp, ctypes.c_size_t]
+        L.lbpc_load_state.argtypes = [vp, vp, ctypes.c_size_t]
+        L.lbpc_destroy.argtypes = [vp]
+        L.lbpc_destroy.restype = None
+        L.lbpc_last_error.argtypes = [vp]
+        L.lbpc_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name not in ("lbpc_destroy", "lbpc_last_error"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def make_config(d: dict) -> Config:
+    c = Config()
+    for name, ctype in Config._fields_:
+        if name not in d:
+            continue
+        v = d[name]
+        if hasattr(ctype, "_length_"):
+            arr = getattr(c, name)
+            for i, x in enumerate(v):
+                arr[i] = x
+        else:
+            setattr(c, name, v)
+    return c
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _check(st, h=None):
+    if st != OK:
+        msg = lib().lbpc_last_error(h)
+        raise LbpcError(st, msg.decode() if msg else "")
+
+
+# ------------------------------------------------ the C entry points ---
+
+def lbpc_workspace_bytes(cfg: dict) -> int:
+    c = make_config(cfg)
+    out = ctypes.c_size_t()
+    _check(lib().lbpc_workspace_bytes(ctypes.byref(c), ctypes.byref(out)))
+    return out.value
+
+
+def lbpc_create(cfg: dict, workspace_ptr: int, workspace_bytes: int,
+                stream_ptr: int):
+    c = make_config(cfg)
+    h = ctypes.c_void_p()
+    _check(lib().lbpc_create(ctypes.byref(c), ctypes.c_void_p(workspace_ptr),
+                             workspace_bytes, ctypes.c_void_p(stream_ptr),
+                             ctypes.byref(h)))
+    return h
+
+
+def lbpc_init_fields(h, rho, ux, uy, T):
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (rho, ux, uy, T)]
+    _check(lib().lbpc_init_fields(h, *map(_dp, arrs)), h)
+
+
+def lbpc_step(h, n: int):
+    _check(lib().lbpc_step(h, int(n)), h)
+
+
+def lbpc_get_rho_u_T(h, shape):
+    out = [np.empty(shape, dtype=np.float64) for _ in range(4)]
+    _check(lib().lbpc_get_rho_u_T(h, *map(_dp, out)), h)
+    return tuple(out)
+
+
+def lbpc_get_diag(h) -> dict:
+    d = Diag()
+    _check(lib().lbpc_get_diag(h, ctypes.byref(d)), h)
+    return {n: getattr(d, n) for n, _ in Diag._fields_ if n != "pad"}
+
+
+def lbpc_save_state(h) -> np.ndarray:
+    nb = ctypes.c_size_t()
+    _check(lib().lbpc_state_bytes(h, ctypes.byref(nb)), h)
+    buf = np.empty(nb.value, dtype=np.uint8)
+    _check(lib().lbpc_save_state(h, buf.ctypes.data_as(ctypes.c_void_p),
+                                 nb.value), h)
+    return buf
+
+
+def lbpc_load_state(h, buf: np.ndarray):
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    _check(lib().lbpc_load_state(h, buf.ctypes.data_as(ctypes.c_void_p),
+                                 buf.nbytes), h)
+
+
+def lbpc_destroy(h):
+    lib().lbpc_destroy(h)
+
+
+# ------------------------------------------------------------- wrapper ---
+
+class Simulation:
+    """One lattice on one GPU: workspace from torch, library handle."""
+
+    def __init__(self, cfg: dict, device: str = "cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the lbpc library needs one")
+        self.cfg = dict(cfg)
+        self.nx, self.ny = int(cfg["nx"]), int(cfg["ny"])
+        self.device = torch.device(device)
+        nbytes = lbpc_workspace_bytes(cfg)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8,
+                              device=self.device)
+        ptr = self.ws.data_ptr()
+        ptr = (ptr + 255) // 256 * 256
+        self.stream = stream if stream is not None else \
+            torch.cuda.current_stream(self.device)
+        self.h = lbpc_create(cfg, ptr, nbytes, self.stream.cuda_stream)
+
+    def init_fields(self, rho, ux, uy, T):
+        lbpc_init_fields(self.h, rho, ux, uy, T)
+
+    def step(self, n: int = 1):
+        lbpc_step(self.h, n)
+
+    def rho_u_T(self):
+        return lbpc_get_rho_u_T(self.h, (self.ny, self.nx))
+
+    def diag(self) -> dict:
+        return lbpc_get_diag(self.h)
+
+    def save_state(self) -> np.ndarray:
+        return lbpc_save_state(self.h)
+
+    def load_state(self, buf):
+        lbpc_load_state(self.h, buf)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lbpc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

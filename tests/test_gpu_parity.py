@@ -1,0 +1,158 @@
+"""FP64 parity: the HIP path through the C ABI against the CPU oracle.
+
+Both sides get the same host FP64 arrays from the shared input module.  The
+bar (stated for FP64 results after 1000 steps): max relative error 1e-11 in
+rho and T (pointwise) and in u (normalised by max |u| of the oracle, since u
+vanishes in places).  The arithmetic differs only in rounding order and FMA
+contraction, so the two agree to a few ulp per step.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1709_04400_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+def _gpu():
+    from paper_1709_04400_amd import lbpc
+    return lbpc
+
+
+def _errors(a, b):
+    (r1, ux1, uy1, T1), (r2, ux2, uy2, T2) = a, b
+    umax = max(np.abs(ux2).max(), np.abs(uy2).max(), 1e-300)
+    return dict(
+        rho=float(np.max(np.abs(r1 - r2) / np.abs(r2))),
+        T=float(np.max(np.abs(T1 - T2) / np.abs(T2))),
+        u=float(max(np.abs(ux1 - ux2).max(), np.abs(uy1 - uy2).max()) / umax))
+
+
+def run_pair(cfg, fields, steps, chunks=1):
+    print(f"\n[parity] {cfg['nx']}x{cfg['ny']} bc={cfg['bc']} "
+          f"prec={cfg['precision']} steps={steps}", flush=True)
+    o = O.Oracle(cfg)
+    o.init_fields(**fields)
+    g = _gpu().Simulation(cfg)
+    g.init_fields(fields["rho"], fields["ux"], fields["uy"], fields["T"])
+    errs = []
+    per = steps // chunks
+    for _ in range(chunks):
+        o.step(per)
+        g.step(per)
+        errs.append(_errors(g.rho_u_T(), o.rho_u_T()))
+    g.close()
+    print(f"[parity] errors {errs[-1]}", flush=True)
+    return errs
+
+
+def _assert_ok(errs, tol=TOL):
+    for e in errs:
+        assert e["rho"] < tol and e["T"] < tol and e["u"] < tol, e
+
+
+def test_init_matches_oracle_exactly_at_step0():
+    cfg, fl = I.static_droplet(40, 36, 10.0)
+    o = O.Oracle(cfg)
+    o.init_fields(**fl)
+    g = _gpu().Simulation(cfg)
+    g.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
+    e = _errors(g.rho_u_T(), o.rho_u_T())
+    g.close()
+    assert e["rho"] < 1e-15 and e["T"] < 1e-15, e
+
+
+def test_static_droplet_1000_steps():
+    """Static droplet: 100 x 100 periodic, R = 25, 1000 steps."""
+    cfg, fl = I.static_droplet(100, 100, 25.0)
+    _assert_ok(run_pair(cfg, fl, 1000, chunks=4))
+
+
+def test_evaporation_cut_open_sides():
+    """128 x 128 cut of the evaporation case: four open fixed-T sides."""
+    cfg, fl = I.evaporation(128, 128 / 6.0, 1.1)
+    _assert_ok(run_pair(cfg, fl, 1000, chunks=2))
+
+
+def test_bubble_cut_walls_hot_spot_gravity():
+    """128 x 128 cut of the boiling case: periodic x, walls in y, hot spot,
+    buoyancy, lambda = rho c_V chi."""
+    cfg, fl = I.bubble(nx=128, ny=128, pool=96, hot_width=14, g=3e-5)
+    _assert_ok(run_pair(cfg, fl, 1000, chunks=2))
+
+
+def test_random_distinct_rates():
+    """Every MRT rate distinct and off 1, so no moment path is masked."""
+    sf, sg = I.random_rates(18)
+    sg[5] = sg[3]
+    cfg, fl = I.static_droplet(64, 64, 16.0)
+    cfg.update(s_f=sf, s_g=sg, gx=2e-5, gy=-1e-5)
+    _assert_ok(run_pair(cfg, fl, 500, chunks=2))
+
+
+def test_compromised_model():
+    cfg, fl = I.static_droplet(64, 48, 14.0)
+    cfg.update(thermal_model=I.THERMAL_COMPROMISED,
+               bc=[I.BC_WALL, I.BC_WALL, I.BC_OPEN, I.BC_OPEN],
+               T_bc=[1.05 * I.T_SAT, 1.02 * I.T_SAT, 1.1 * I.T_SAT,
+                     1.0 * I.T_SAT])
+    _assert_ok(run_pair(cfg, fl, 400))
+
+
+@pytest.mark.parametrize("tile_h", [16, 37])
+def test_ragged_tiles_many_blocks(monkeypatch, tile_h):
+    """nx = 300 needs two strips of 252 columns (ragged second strip); small
+    row runs give many blocks with ragged last runs."""
+    monkeypatch.setenv("LBPC_TILE_H", str(tile_h))
+    cfg, fl = I.evaporation(300, 40.0, 1.1)
+    cfg.update(ny=150, bc=[I.BC_PERIODIC, I.BC_PERIODIC, I.BC_WALL, I.BC_OPEN],
+               hot_x0=120, hot_x1=180, T_hot=1.15 * I.T_SAT, gy=-2e-5)
+    fl = I.droplet_fields(300, 150, 40.0)
+    _assert_ok(run_pair(cfg, fl, 200))
+
+
+def test_save_load_roundtrip_matches_uninterrupted():
+    cfg, fl = I.bubble(nx=64, ny=64, pool=40, hot_width=8)
+    g = _gpu().Simulation(cfg)
+    g.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
+    g.step(30)
+    st = g.save_state()
+    g.step(20)
+    ref = g.rho_u_T()
+    g2 = _gpu().Simulation(cfg)
+    g2.load_state(st)
+    g2.step(20)
+    out = g2.rho_u_T()
+    for a, b in zip(ref, out):
+        assert np.array_equal(a, b)
+    # the saved state is the oracle's canonical state
+    o = O.Oracle(cfg)
+    o.init_fields(**fl)
+    o.step(30)
+    ost = o.get_state()
+    n = cfg["nx"] * cfg["ny"]
+    f = st[:9 * n * 8].view(np.float64).reshape(9, cfg["ny"], cfg["nx"])
+    assert np.max(np.abs(f - ost["f"])) < 1e-12
+    g.close()
+    g2.close()
+
+
+def test_diag_matches_oracle():
+    cfg, fl = I.evaporation(96, 20.0, 1.1)
+    o = O.Oracle(cfg)
+    o.init_fields(**fl)
+    g = _gpu().Simulation(cfg)
+    g.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
+    o.step(100)
+    g.step(100)
+    do, dg = o.diag(), g.diag()
+    g.close()
+    for k in ("mass", "sum_T", "sum_rhocvT", "liquid_area", "radius",
+              "max_speed"):
+        assert np.isclose(dg[k], do[k], rtol=1e-11, atol=1e-14), k
+    assert dg["radius_count"] == do["radius_count"]
+    assert dg["step"] == 100 and not dg["nonfinite"]
