@@ -222,20 +222,27 @@ lbpc_status lbpc_create(const lbpc_config* cfg, void* dev_workspace,
     p.bc[i] = cfg->bc[i];
     p.T_bc[i] = cfg->T_bc[i];
   }
-  p.W = lbpc::BLOCK - 2 * lbpc::HALO;
-  p.nbx = (cfg->nx + p.W - 1) / p.W;
   {
-    // rows per block: enough blocks to fill 256 CUs twice over, at least
-    // 16 rows so the 4-row warm-up stays small
+    // strip width (threads per block) and rows per block; LBPC_TILE_BW and
+    // LBPC_TILE_H override the defaults
+    int bw = env_int("LBPC_TILE_BW", 256);
+    if (bw != 64 && bw != 128 && bw != 256) bw = 256;
+    p.bw = bw;
+    p.W = bw - 2 * lbpc::HALO;
+    p.nbx = (cfg->nx + p.W - 1) / p.W;
     int h_rows = env_int("LBPC_TILE_H", 0);
     if (h_rows <= 0) {
-      long long want = 2048 / p.nbx;
+      // enough blocks to give each of the 256 CUs several, and at least 16
+      // rows per block so the 4-row warm-up stays small
+      long long want = (2048LL * 256 / bw) / p.nbx;
       if (want < 1) want = 1;
       h_rows = (int)((cfg->ny + want - 1) / want);
       if (h_rows < 16) h_rows = 16;
       if (h_rows > 256) h_rows = 256;
     }
     p.H = h_rows;
+    p.nby = (cfg->ny + p.H - 1) / p.H;
+    p.xcd_order = env_int("LBPC_XCD_ORDER", 1);
   }
   p.hot_x0 = cfg->hot_x0;
   p.hot_x1 = cfg->hot_x1;
@@ -257,6 +264,12 @@ lbpc_status lbpc_create(const lbpc_config* cfg, void* dev_workspace,
   p.lambda0 = cfg->lambda0;
   p.chi = cfg->chi;
   p.k_th = (1.0 / cfg->s_g[3] - 0.5) * (1.0 / 3.0);  // Eq. (A13), c_s^2 = 1/3
+  p.inv_Tc = 1.0 / p.Tc;
+  p.two_over_G = 2.0 / cfg->G;
+  p.inv_cv = 1.0 / cfg->cv;
+  p.lam_over_cv = cfg->lambda0 / cfg->cv;
+  p.sig1 = 12.0 * cfg->sigma * cfg->G * cfg->G / (1.0 / cfg->s_f[1] - 0.5);
+  p.sig2 = 12.0 * cfg->sigma * cfg->G * cfg->G / (1.0 / cfg->s_f[2] - 0.5);
   p.lambda_mode = cfg->lambda_mode;
   p.improved = cfg->thermal_model == LBPC_THERMAL_IMPROVED;
   p.rho_ref = cfg->rho_ref;

@@ -10,7 +10,6 @@
 namespace lbpc {
 
 constexpr int Q = 9;
-constexpr int BLOCK = 256;      // threads per block of the fused step kernel
 constexpr int HALO = 2;         // columns of halo on each side of a strip
 constexpr int RING = 5;         // rows held in the LDS ring buffers
 
@@ -24,7 +23,9 @@ struct StepParams {
   int perx, pery;          // 1 if that axis is periodic
   int bc[4];               // side kinds x-, x+, y-, y+
   int W, H;                // interior columns / rows per block
-  int nbx;                 // blocks along x
+  int nbx, nby;            // blocks along x and y
+  int bw;                  // threads per block (strip width incl. halo)
+  int xcd_order;           // 1: blocks of one XCD take x-adjacent strips
   int hot_x0, hot_x1;
   double T_bc[4], T_hot;
   // EOS (Eq. 56) and flow model
@@ -36,6 +37,9 @@ struct StepParams {
   double s_g[9];
   double cv, lambda0, chi, k_th;
   int lambda_mode, improved;
+  // derived on the host: 1/Tc, 2/G, 1/c_V, lambda0/c_V and the sigma terms
+  // 12 sigma G^2 / (1/s_f[k] - 1/2), k = 1, 2 (|F_m|^2/psi^2 = G^2 |s|^2)
+  double inv_Tc, two_over_G, inv_cv, lam_over_cv, sig1, sig2;
   // storage shift (rho_ref, T_ref of the shifted forms)
   double rho_ref, T_ref;
   // state flags

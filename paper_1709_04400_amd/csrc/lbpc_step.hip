@@ -9,15 +9,18 @@
 //   * a block of 256 threads (4 wave64) owns a strip of W = 252 columns plus
 //     2 halo columns per side (one column per thread) and a run of H rows;
 //     it marches up the rows.  Iteration r:
-//       A(r)   pull f, g at row r; rho, j, T, psi -> LDS ring (5 rows)
+//       A(r)   rho, j, T of row r from its pulled f, g; EOS (FP64): psi and
+//              T (dp/dT)_rho -> LDS ring (5 rows) / registers
 //       B(r-1) interaction force from psi rows r-2..r, buoyancy, velocity
 //              -> LDS ring; flow MRT collision of row r-1, store f*
+//       pull of row r+1 issued here, in flight during C2
 //       C(r-2) isotropic differences of T, v (and rho) on rows r-3..r-1,
 //              thermal source phi, S0, improved thermal MRT collision of
 //              row r-2, store g*, phi
-//     so every pulled value is loaded from memory exactly once per block
-//     (halo columns aside) and the 2-hop stencil dependence (div v needs v
-//     one node away, which needs psi two nodes away) never goes to memory;
+//     so every pulled value is loaded from memory once per block (halo
+//     columns and the 4 warm-up rows aside) and the 2-hop stencil dependence
+//     (div v needs v one node away, which needs psi two nodes away) never
+//     goes to memory;
 //   * pulled f is held in registers for one row, pulled g for two.
 // Non-periodic sides: the pull applies bounce-back / open rules at edge
 // nodes, and LDS reads of a ghost neighbour take the nearest lattice node's
@@ -26,8 +29,34 @@
 
 namespace lbpc {
 
-template <int P, bool GEN>
-__global__ __launch_bounds__(BLOCK, 2) void k_step(StepParams p) {
+// Tile of this block.  Workgroups are dealt to the 8 XCDs round-robin; with
+// xcd_order the tiles are renumbered so that the blocks one XCD runs at the
+// same time are x-neighbours sharing halo columns in that XCD's L2.
+__device__ __forceinline__ void block_tile(const StepParams& p, int& bx,
+                                           int& by) {
+  const int nb = p.nbx * p.nby;
+  int b = blockIdx.x;
+  if (p.xcd_order) {
+    // XCD j runs blocks j, j+8, j+16, ...; the first `full` XCDs get
+    // `per` tiles each, the others per - 1, in consecutive tile order
+    const int per = (nb + 7) / 8;
+    const int xcd = b % 8, k = b / 8;
+    const int full = nb - 8 * (per - 1);
+    b = xcd < full ? xcd * per + k
+                   : full * per + (xcd - full) * (per - 1) + k;
+  }
+  by = b / p.nbx;
+  bx = b - by * p.nbx;
+}
+
+// waves per SIMD the register budget is sized for: the FP64 form holds its
+// queues of pulled values in 64-bit registers
+template <int P> struct StepOcc { static constexpr int waves = P == 0 ? 2 : 3; };
+
+template <int P, bool GEN, int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((
+    amdgpu_waves_per_eu(StepOcc<P>::waves, StepOcc<P>::waves))) void
+k_step(StepParams p) {
   using Tr = Prec<P>;
   using S = typename Tr::S;
   using C = typename Tr::C;
@@ -41,8 +70,10 @@ __global__ __launch_bounds__(BLOCK, 2) void k_step(StepParams p) {
   const int t = threadIdx.x;
   const int nx = p.nx, ny = p.ny;
   const long long N = p.N;
-  const int X0 = blockIdx.x * p.W, X1 = min(X0 + p.W, nx);
-  const int Y0 = blockIdx.y * p.H, Y1 = min(Y0 + p.H, ny);
+  int bx, by;
+  block_tile(p, bx, by);
+  const int X0 = bx * p.W, X1 = min(X0 + p.W, nx);
+  const int Y0 = by * p.H, Y1 = min(Y0 + p.H, ny);
   const int c = X0 - HALO + t;  // unwrapped column of this thread
 
   const S* __restrict__ fin = static_cast<const S*>(p.fin);
@@ -71,11 +102,8 @@ __global__ __launch_bounds__(BLOCK, 2) void k_step(StepParams p) {
     if (c + 1 >= nx) ttp = t;
   }
 
-  // shifts of the shifted storage forms
   C fsh[Q], gsh[Q];
   storage_shifts<P>(p, fsh, gsh);
-
-  // rates in compute precision
   C sf[Q], sg[Q];
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
@@ -83,58 +111,102 @@ __global__ __launch_bounds__(BLOCK, 2) void k_step(StepParams p) {
     sg[a] = C(p.s_g[a]);
   }
 
-  // register queues: pulled f of row r-1, pulled g of rows r-1 and r-2
-  C fq1[Q], gq1[Q], gq2[Q];
-#pragma unroll
-  for (int a = 0; a < Q; ++a) fq1[a] = gq1[a] = gq2[a] = C(0);
-  C jx1 = C(0), jy1 = C(0);
+  // row r -> wrapped row, or -1 for a ghost row of a non-periodic y side
+  auto wrap_row = [&](int r) -> int {
+    if (r >= 0 && r < ny) return r;
+    if (!p.pery) return -1;
+    return r < 0 ? r + ny : r - ny;
+  };
 
-  const int rbeg = Y0 - 2, rend = Y1 + 2;
-  for (int r = rbeg; r < rend; ++r) {
-    const int i = r - rbeg;
-    const int sl0 = i % RING;                // slot of row r
-    const int sl1 = (i + RING - 1) % RING;   // row r-1
-    const int sl2 = (i + RING - 2) % RING;   // row r-2
-    const int sl3 = (i + RING - 3) % RING;   // row r-3
+  // pulled values: row r (loaded one iteration ahead), queues of f (row r-1)
+  // and g (rows r-1, r-2); j (row r-1), T dp/dT (rows r-1, r-2) and 1/rho
+  // (row r-2) of this thread's own column
+  C fc[Q], gc[Q], fq1[Q], gq1[Q], gq2[Q];
+#pragma unroll
+  for (int a = 0; a < Q; ++a) fc[a] = gc[a] = fq1[a] = gq1[a] = gq2[a] = C(0);
+  C jx1 = C(0), jy1 = C(0), tdp1 = C(0), tdp2 = C(0), irq = C(0);
+
+  // march direction alternates between vertically adjacent row runs, so the
+  // rows two runs share are pulled by both at the same time (both at their
+  // start or both at their end) and the second pull is served by L2
+  const int dir = (by & 1) ? -1 : 1;
+  const int nit = Y1 - Y0 + 4;
+  const int rfirst = dir > 0 ? Y0 - 2 : Y1 + 1;
+  {
+    const int rw = wrap_row(rfirst);
+    if (doA && rw >= 0)
+      pull_node<P, GEN>(p, fin, gin, cw, rw, fsh, gsh, fc, gc);
+  }
+
+  for (int it = 0; it < nit; ++it) {
+    const int r = rfirst + dir * it;
+    const int sl0 = it % RING;                // slot of row r
+    const int sl1 = (it + RING - 1) % RING;   // row r - dir
+    const int sl2 = (it + RING - 2) % RING;   // row r - 2 dir
+    const int sl3 = (it + RING - 3) % RING;   // row r - 3 dir
 
     // ------------------------------------------------------------ A(r)
-    C fn[Q], gn[Q];
-    C jxn = C(0), jyn = C(0);
-    {
-      int rw = r;
-      bool ghostr = false;
-      if (r < 0 || r >= ny) {
-        if (p.pery)
-          rw = r < 0 ? r + ny : r - ny;
-        else
-          ghostr = true;
+    C jxn = C(0), jyn = C(0), tdpn = C(0);
+    const int rwA = wrap_row(r);
+    if (doA && rwA >= 0) {
+      const C sa = fc[1] + fc[2] + fc[3] + fc[4];
+      const C sd = fc[5] + fc[6] + fc[7] + fc[8];
+      const C rho = fc[0] + sa + sd;
+      jxn = (fc[1] - fc[3]) + (fc[5] - fc[6] - fc[7] + fc[8]);
+      jyn = (fc[2] - fc[4]) + (fc[5] + fc[6] - fc[7] - fc[8]);
+      const C T = gc[0] + (gc[1] + gc[2] + gc[3] + gc[4]) +
+                  (gc[5] + gc[6] + gc[7] + gc[8]);
+      // Peng-Robinson EOS, Eq. (56), in FP64 with one reciprocal:
+      //   p = (rho R T D2 - a th rho^2 D1) / (D1 D2),
+      //   T dp/dT = (rho R T D2 + a kappa s sqrt(T/Tc) rho^2 D1) / (D1 D2),
+      // D1 = 1 - b rho, D2 = 1 + 2 b rho - b^2 rho^2, s = 1 + kappa (1 -
+      // sqrt(T/Tc)), th = s^2 (using T dth/dT = -kappa s sqrt(T/Tc))
+      double psi;
+      if constexpr (sizeof(C) == 8) {
+        const double rd = rho, Td = T;
+        const double sq = sqrt(Td * p.inv_Tc);
+        const double s = 1.0 + p.kappa * (1.0 - sq);
+        const double brho = p.b * rd;
+        const double D1 = 1.0 - brho, D2 = 1.0 + brho * (2.0 - brho);
+        const double inv = 1.0 / (D1 * D2);
+        const double rRT = rd * p.R * Td * D2;
+        const double ar2 = p.a * rd * rd * D1;
+        const double pe = (rRT - ar2 * s * s) * inv;
+        const double psi2 = p.two_over_G * (pe - rd * (1.0 / 3.0));
+        psi = sqrt(psi2 > 0.0 ? psi2 : 0.0);
+        tdpn = C((rRT + ar2 * p.kappa * s * sq) * inv);
+      } else {
+        // FP32 arithmetic: the smooth factors (sqrt(T/Tc), s, 1/(D1 D2))
+        // in FP32, the cancelling combinations (repulsive - attractive
+        // pressure, then p - rho c_s^2) in FP64
+        const float sq = sqrtf(T * float(p.inv_Tc));
+        const float s = 1.0f + float(p.kappa) * (1.0f - sq);
+        const float brho = float(p.b) * rho;
+        const float D1 = 1.0f - brho, D2 = 1.0f + brho * (2.0f - brho);
+        const float inv = 1.0f / (D1 * D2);
+        const double rd = rho;
+        const double rRT = rd * p.R * (double)T * (double)D2;
+        const double ar2 = p.a * rd * rd * (double)D1;
+        const double th = (double)s * (double)s;
+        const double pe = (rRT - ar2 * th) * (double)inv;
+        const double psi2 = p.two_over_G * (pe - rd * (1.0 / 3.0));
+        psi = sqrtf(float(psi2 > 0.0 ? psi2 : 0.0));
+        tdpn = C((rRT + ar2 * (p.kappa * (double)(s * sq))) * (double)inv);
       }
-#pragma unroll
-      for (int a = 0; a < Q; ++a) fn[a] = gn[a] = C(0);
-      if (doA && !ghostr) {
-        pull_node<P, GEN>(p, fin, gin, cw, rw, fsh, gsh, fn, gn);
-        C sa = fn[1] + fn[2] + fn[3] + fn[4];
-        C sd = fn[5] + fn[6] + fn[7] + fn[8];
-        C rho = fn[0] + sa + sd;
-        jxn = (fn[1] - fn[3]) + (fn[5] - fn[6] - fn[7] + fn[8]);
-        jyn = (fn[2] - fn[4]) + (fn[5] + fn[6] - fn[7] - fn[8]);
-        C T = gn[0] + (gn[1] + gn[2] + gn[3] + gn[4]) +
-              (gn[5] + gn[6] + gn[7] + gn[8]);
-        double psi = pseudo_psi(p, (double)rho, (double)T);
-        s_rho[sl0][t] = rho;
-        s_T[sl0][t] = T;
-        s_psi[sl0][t] = C(psi);
-      }
+      s_rho[sl0][t] = rho;
+      s_T[sl0][t] = T;
+      s_psi[sl0][t] = C(psi);
     }
     __syncthreads();
 
     // ------------------------------------------------ B(r-1) and C1(r-1)
+    C irn = C(0);
     {
-      const int rb = r - 1;
-      bool ghostr = (rb < 0 || rb >= ny) && !p.pery;
-      if (doB && !ghostr && r >= Y0) {
+      const int rb = r - dir;
+      const bool ghostr = (rb < 0 || rb >= ny) && !p.pery;
+      if (doB && !ghostr && rb >= Y0 - 1 && rb <= Y1) {
         // psi rows rb-1, rb, rb+1 (clamped at non-periodic y sides)
-        int sm = sl2, sp = sl0;
+        int sm = dir > 0 ? sl2 : sl0, sp = dir > 0 ? sl0 : sl2;
         if (GEN && !p.pery) {
           if (rb - 1 < 0) sm = sl1;
           if (rb + 1 >= ny) sp = sl1;
@@ -144,22 +216,25 @@ __global__ __launch_bounds__(BLOCK, 2) void k_step(StepParams p) {
         const C pN = s_psi[sp][t], pS = s_psi[sm][t];
         const C pNE = s_psi[sp][ttp], pNW = s_psi[sp][ttm];
         const C pSE = s_psi[sm][ttp], pSW = s_psi[sm][ttm];
+        // F_m = -G psi sum_a w_a psi(x+e_a) e_a = -G psi (sx, sy)
         const C sx = C(1.0 / 3.0) * (pE - pW) +
                      C(1.0 / 12.0) * ((pNE - pNW) + (pSE - pSW));
         const C sy = C(1.0 / 3.0) * (pN - pS) +
                      C(1.0 / 12.0) * ((pNE - pSE) + (pNW - pSW));
-        const C mG = C(-p.G);
-        const C Fmx = mG * pc * sx, Fmy = mG * pc * sy;
+        const C mGpc = C(-p.G) * pc;
+        const C Fmx = mGpc * sx, Fmy = mGpc * sy;
         const C rho = s_rho[sl1][t];
         const C drho = rho - C(p.rho_ave);
         const C Fx = Fmx + drho * C(p.gx), Fy = Fmy + drho * C(p.gy);
-        const C vx = (jx1 + C(0.5) * Fx) / rho;
-        const C vy = (jy1 + C(0.5) * Fy) / rho;
+        irn = C(1) / rho;
+        const C vx = (jx1 + C(0.5) * Fx) * irn;
+        const C vy = (jy1 + C(0.5) * Fy) * irn;
         s_vx[sl1][t] = vx;
         s_vy[sl1][t] = vy;
 
         if (doC && rb >= Y0 && rb < Y1) {
-          // flow MRT collision with the forcing scheme of the flow model
+          // flow MRT collision with the forcing scheme of the flow model;
+          // |F_m|^2 / psi^2 = G^2 (sx^2 + sy^2), folded into sig1, sig2
           C m[Q], ms[Q], fo[Q];
           to_moments(fq1, m);
           const C v2 = vx * vx + vy * vy;
@@ -174,13 +249,11 @@ __global__ __launch_bounds__(BLOCK, 2) void k_step(StepParams p) {
           meq[7] = rho * (vx * vx - vy * vy);
           meq[8] = rho * vx * vy;
           const C vF = vx * Fx + vy * Fy;
-          const C Fm2 = Fmx * Fmx + Fmy * Fmy;
-          const C psi2 = pc * pc;
-          const C sig12 = C(12.0 * p.sigma);
+          const C s2 = sx * sx + sy * sy;
           C Sf[Q];
           Sf[0] = C(0);
-          Sf[1] = C(6) * vF + sig12 * Fm2 / (psi2 * (C(1) / sf[1] - C(0.5)));
-          Sf[2] = -C(6) * vF - sig12 * Fm2 / (psi2 * (C(1) / sf[2] - C(0.5)));
+          Sf[1] = C(6) * vF + C(p.sig1) * s2;
+          Sf[2] = -C(6) * vF - C(p.sig2) * s2;
           Sf[3] = Fx;
           Sf[4] = -Fx;
           Sf[5] = Fy;
@@ -198,14 +271,25 @@ __global__ __launch_bounds__(BLOCK, 2) void k_step(StepParams p) {
         }
       }
     }
+    // f of row r waits one row for its collision; row r + dir is pulled now
+#pragma unroll
+    for (int a = 0; a < Q; ++a) fq1[a] = fc[a];
+    C gn[Q];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) gn[a] = C(0);
+    {
+      const int rwn = (it + 1 < nit) ? wrap_row(r + dir) : -1;
+      if (doA && rwn >= 0)
+        pull_node<P, GEN>(p, fin, gin, cw, rwn, fsh, gsh, fc, gn);
+    }
     __syncthreads();
 
     // -------------------------------------------------------------- C2(r-2)
     {
-      const int yc = r - 2;
+      const int yc = r - 2 * dir;
+      const int slN = dir > 0 ? sl1 : sl3, slS = dir > 0 ? sl3 : sl1;
       if (doC && yc >= Y0 && yc < Y1) {
         const C T = s_T[sl2][t];
-        const C rho = s_rho[sl2][t];
         const C vx = s_vx[sl2][t], vy = s_vy[sl2][t];
         // neighbour values (E, W, N, S, NE, NW, SE, SW)
         C Tn[8], vxn[8], vyn[8], rn[8];
@@ -217,11 +301,11 @@ __global__ __launch_bounds__(BLOCK, 2) void k_step(StepParams p) {
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
             const int tt = DX[k] > 0 ? ttp : (DX[k] < 0 ? ttm : t);
-            const int sl = DY[k] > 0 ? sl1 : (DY[k] < 0 ? sl3 : sl2);
+            const int sl = DY[k] > 0 ? slN : (DY[k] < 0 ? slS : sl2);
             Tn[k] = s_T[sl][tt];
             vxn[k] = s_vx[sl][tt];
             vyn[k] = s_vy[sl][tt];
-            rn[k] = s_rho[sl][tt];
+            rn[k] = p.lambda_mode ? s_rho[sl][tt] : C(0);
           }
         } else {
 #pragma unroll
@@ -231,7 +315,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_step(StepParams p) {
             // fall back to this node's own column / row
             int tt = t + DX[k];
             if (!p.perx && (c + DX[k] < 0 || c + DX[k] >= nx)) tt = t;
-            int sl = DY[k] > 0 ? sl1 : (DY[k] < 0 ? sl3 : sl2);
+            int sl = DY[k] > 0 ? slN : (DY[k] < 0 ? slS : sl2);
             if (!p.pery && (yc + DY[k] < 0 || yc + DY[k] >= ny)) sl = sl2;
             rn[k] = s_rho[sl][tt];
             if (gh.kind == GH_INSIDE) {
@@ -260,21 +344,21 @@ __global__ __launch_bounds__(BLOCK, 2) void k_step(StepParams p) {
                        twelfth * ((vxn[4] - vxn[5]) + (vxn[6] - vxn[7])) +
                        third * (vyn[2] - vyn[3]) +
                        twelfth * ((vyn[4] - vyn[6]) + (vyn[5] - vyn[7]));
-        const C rcv = rho * C(p.cv);
-        C div_lam_gradT;
+        // phi of Eq. (28): div(lambda grad T)/(rho c_V) - k lap T
+        //                  + (T - T (dp/dT)/(rho c_V)) div v
+        C lam_term;
         if (p.lambda_mode == 0) {
-          div_lam_gradT = C(p.lambda0) * lapT;
+          lam_term = C(p.lam_over_cv) * irq * lapT;
         } else {
+          // lambda = rho c_V chi: chi (lap T + grad rho . grad T / rho)
           const C drx = third * (rn[0] - rn[1]) +
                         twelfth * ((rn[4] - rn[5]) + (rn[6] - rn[7]));
           const C dry = third * (rn[2] - rn[3]) +
                         twelfth * ((rn[4] - rn[6]) + (rn[5] - rn[7]));
-          const C cvchi = C(p.cv * p.chi);
-          div_lam_gradT = rho * cvchi * lapT + cvchi * (drx * dTx + dry * dTy);
+          lam_term = C(p.chi) * (lapT + irq * (drx * dTx + dry * dTy));
         }
-        const C dpdT = C(pr_dpdT(p, (double)rho, (double)T));
-        const C phi = div_lam_gradT / rcv - C(p.k_th) * lapT +
-                      T * (C(1) - dpdT / rcv) * divv;
+        const C phi = lam_term - C(p.k_th) * lapT +
+                      (T - tdp2 * irq * C(p.inv_cv)) * divv;
         const long long o = (long long)yc * nx + c;
         C S0 = phi;
         if (p.improved) {
@@ -305,28 +389,39 @@ __global__ __launch_bounds__(BLOCK, 2) void k_step(StepParams p) {
       }
     }
 
-    // rotate the register queues
+    // rotate the per-column queues
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-      fq1[a] = fn[a];
       gq2[a] = gq1[a];
-      gq1[a] = gn[a];
+      gq1[a] = gc[a];
+      gc[a] = gn[a];
     }
     jx1 = jxn;
     jy1 = jyn;
+    tdp2 = tdp1;
+    tdp1 = tdpn;
+    irq = irn;
   }
 }
 
 // host-side launcher: one instantiation per storage precision and boundary
 // mode (GEN = some side is not periodic)
 hipError_t launch_step(const StepParams& p, int prec, hipStream_t s) {
-  dim3 grid(p.nbx, (p.ny + p.H - 1) / p.H);
+  const dim3 grid(p.nbx * p.nby);
   const bool gen = !(p.perx && p.pery);
-#define LBPC_LAUNCH(PR)                                                   \
-  if (gen)                                                                \
-    hipLaunchKernelGGL((k_step<PR, true>), grid, dim3(BLOCK), 0, s, p);   \
-  else                                                                    \
-    hipLaunchKernelGGL((k_step<PR, false>), grid, dim3(BLOCK), 0, s, p);
+#define LBPC_LAUNCH_BW(PR, BW)                                              \
+  if (gen)                                                                  \
+    hipLaunchKernelGGL((k_step<PR, true, BW>), grid, dim3(BW), 0, s, p);    \
+  else                                                                      \
+    hipLaunchKernelGGL((k_step<PR, false, BW>), grid, dim3(BW), 0, s, p);
+#define LBPC_LAUNCH(PR)                                                     \
+  if (p.bw == 64) {                                                         \
+    LBPC_LAUNCH_BW(PR, 64)                                                  \
+  } else if (p.bw == 128) {                                                 \
+    LBPC_LAUNCH_BW(PR, 128)                                                 \
+  } else {                                                                  \
+    LBPC_LAUNCH_BW(PR, 256)                                                 \
+  }
   switch (prec) {
     case 0: LBPC_LAUNCH(0); break;
     case 1: LBPC_LAUNCH(1); break;
@@ -335,6 +430,7 @@ hipError_t launch_step(const StepParams& p, int prec, hipStream_t s) {
     default: return hipErrorInvalidValue;
   }
 #undef LBPC_LAUNCH
+#undef LBPC_LAUNCH_BW
   return hipGetLastError();
 }
 
