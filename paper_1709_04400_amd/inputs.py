@@ -55,7 +55,7 @@ def base_config(nx: int, ny: int, **over) -> dict:
         lambda0=LAMBDA_D2, chi=CHI_BUBBLE,
         s_f=list(S_F_DEFAULT), s_g=list(S_G_DEFAULT),
         G=-1.0, sigma=SIGMA_DEFAULT, gx=0.0, gy=0.0,
-        T_bc=[T_SAT] * 4, T_hot=T_SAT, rho_ref=0.0, T_ref=0.0,
+        T_bc=[T_SAT] * 4, T_hot=T_SAT, rho_ref=RHO_V, T_ref=T_SAT,
         rho_v=RHO_V, rho_l=RHO_L,
         nx=int(nx), ny=int(ny), bc=[BC_PERIODIC] * 4,
         hot_x0=0, hot_x1=0, lambda_mode=LAMBDA_CONST,
@@ -125,6 +125,13 @@ def bubble(nx=400, ny=800, pool=600, hot_width=40, T_hot_over_Ts=1.2,
 CV_SPINODAL = 20.0
 
 
+# reference of the shifted storage forms: f is stored as f_a - w_a RHO_REF.
+# Zero-centring the vapour, whose populations are the smallest, keeps their
+# relative quantisation error lowest (a mean-density reference leaves FP16
+# vapour populations with ~1% steps and the film inverts within 24000 steps).
+RHO_REF_SHIFT = RHO_V
+
+
 def spinodal(n=4096, seed=4400, precision=FP64, rho_ref=None):
     """Periodic n x n; rho = mean coexistence density (1 + U(-0.01, 0.01)),
     T = T_sat (1 + U(-0.005, 0.005)), u = 0; c_V = CV_SPINODAL."""
@@ -133,7 +140,7 @@ def spinodal(n=4096, seed=4400, precision=FP64, rho_ref=None):
     rho = mean * (1.0 + rng.uniform(-0.01, 0.01, size=(n, n)))
     T = T_SAT * (1.0 + rng.uniform(-0.005, 0.005, size=(n, n)))
     cfg = base_config(n, n, precision=precision, cv=CV_SPINODAL,
-                      rho_ref=mean if rho_ref is None else rho_ref,
+                      rho_ref=RHO_REF_SHIFT if rho_ref is None else rho_ref,
                       T_ref=T_SAT)
     z = np.zeros((n, n))
     return cfg, dict(rho=rho, ux=z, uy=z.copy(), T=T)
