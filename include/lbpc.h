@@ -170,6 +170,48 @@ void lbpc_destroy(lbpc_handle *h);
  * lbpc_create / lbpc_workspace_bytes when h is NULL).  Never NULL. */
 const char *lbpc_last_error(const lbpc_handle *h);
 
+/* ------------------------------------------------------------- batches --
+ * Many independent lattices (different sizes, sides and parameters, one
+ * storage precision) advanced together: one persistent kernel launch per
+ * time step walks a list of (lattice, tile) work items, costliest first.
+ * Every lattice computes exactly what a single handle with its
+ * configuration computes.  With a non-NULL stream, steady-state steps are
+ * replayed from a captured hipGraph of two steps (one ping-pong period). */
+typedef struct lbpc_batch lbpc_batch;
+
+/* Device bytes for the batch (all lattices, the work list, shared scratch). */
+lbpc_status lbpc_batch_workspace_bytes(const lbpc_config *cfgs, int32_t n,
+                                       size_t *bytes);
+/* cfgs[0..n-1]: one configuration per lattice, same precision, flags 0. */
+lbpc_status lbpc_batch_create(const lbpc_config *cfgs, int32_t n,
+                              void *dev_workspace, size_t workspace_bytes,
+                              void *hip_stream, lbpc_batch **out);
+/* Initial fields of lattice c (host FP64 [ny][nx], copied; same rules as
+ * lbpc_init_fields).  Allowed only before the first step; every lattice must
+ * be initialised before lbpc_batch_step. */
+lbpc_status lbpc_batch_init_fields(lbpc_batch *b, int32_t c,
+                                   const double *rho, const double *ux,
+                                   const double *uy, const double *T);
+/* Tile shape: threads per block (64, 128 or 256) and rows per tile (>= 4). */
+lbpc_status lbpc_batch_set_tiles(lbpc_batch *b, int32_t block_width,
+                                 int32_t rows);
+/* Times `steps` launches of each candidate tile shape on the initialised
+ * state (which it leaves unchanged: allowed only before the first step),
+ * keeps the fastest and reports it.  Blocks until done. */
+lbpc_status lbpc_batch_autotune(lbpc_batch *b, int32_t steps,
+                                int32_t *block_width, int32_t *rows,
+                                double *ms_per_step);
+/* Enqueues n coupled time steps of every lattice. */
+lbpc_status lbpc_batch_step(lbpc_batch *b, int64_t n);
+/* Per-lattice readback, as lbpc_get_rho_u_T / lbpc_get_diag (synchronising). */
+lbpc_status lbpc_batch_get_rho_u_T(lbpc_batch *b, int32_t c, double *rho,
+                                   double *ux, double *uy, double *T);
+lbpc_status lbpc_batch_get_diag(lbpc_batch *b, int32_t c, lbpc_diag *out);
+/* Lattice-node updates per step summed over the batch (for throughput). */
+lbpc_status lbpc_batch_nodes(const lbpc_batch *b, int64_t *nodes);
+void lbpc_batch_destroy(lbpc_batch *b);
+const char *lbpc_batch_last_error(const lbpc_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbpc.so")
-SOURCES = ["lbpc_api.cpp", "lbpc_step.hip", "lbpc_aux.hip"]
+SOURCES = ["lbpc_api.cpp", "lbpc_batch.cpp", "lbpc_step.hip", "lbpc_aux.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -10,114 +10,12 @@
 #include <string>
 #include <vector>
 
-#include "../../include/lbpc.h"
-#include "lbpc_device.h"
+#include "lbpc_host.h"
 
-namespace lbpc {
-hipError_t launch_step(const StepParams& p, int prec, hipStream_t s);
-hipError_t launch_init(const StepParams& p, int prec, const double* in,
-                       hipStream_t s);
-hipError_t launch_macro(const StepParams& p, int prec, double* io,
-                        hipStream_t s);
-hipError_t launch_diag(const StepParams& p, const double* io, double rho_v,
-                       double rho_l, double* partial, double* out,
-                       hipStream_t s);
-hipError_t launch_canon(const StepParams& p, int prec, int which, double* out,
-                        hipStream_t s);
-hipError_t launch_load(const StepParams& p, int prec, int which,
-                       const double* in, hipStream_t s);
-hipError_t launch_phi_out(const StepParams& p, int prec, double* out,
-                          hipStream_t s);
-hipError_t launch_phi_in(const StepParams& p, int prec, const double* in,
-                         hipStream_t s);
-int diag_blocks(long long N);
-}  // namespace lbpc
-
-using lbpc::StepParams;
+using namespace lbpc_host;
 
 namespace {
-
 thread_local std::string g_err = "";
-
-constexpr size_t ALIGN = 256;
-size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
-
-size_t store_bytes(int prec) {
-  return prec == LBPC_FP64 ? 8 : (prec == LBPC_FP16_SHIFTED ? 2 : 4);
-}
-size_t compute_bytes(int prec) { return prec == LBPC_FP64 ? 8 : 4; }
-
-struct Layout {
-  size_t dist[2][2];  // offsets of f / g of buffer 0 / 1
-  size_t phi, scratch, partial, diag_out;
-  size_t total;
-};
-
-Layout plan(const lbpc_config& c) {
-  Layout L;
-  const size_t N = (size_t)c.nx * (size_t)c.ny;
-  const size_t dbytes = align_up(9 * N * store_bytes(c.precision));
-  size_t off = 0;
-  for (int b = 0; b < 2; ++b)
-    for (int k = 0; k < 2; ++k) {
-      L.dist[b][k] = off;
-      off += dbytes;
-    }
-  L.phi = off;
-  off += align_up(N * compute_bytes(c.precision));
-  L.scratch = off;
-  off += align_up(5 * N * sizeof(double));
-  L.partial = off;
-  off += align_up((size_t)lbpc::diag_blocks((long long)N) * 8 * sizeof(double));
-  L.diag_out = off;
-  off += align_up(8 * sizeof(double));
-  L.total = off;
-  return L;
-}
-
-double pr_Tc(const lbpc_config& c) {
-  return 0.0778 * c.a / (0.45724 * c.b * c.R);
-}
-double pr_kappa(double w) { return 0.37464 + 1.54226 * w - 0.26992 * w * w; }
-
-double host_psi2(const lbpc_config& c, double rho, double T) {
-  const double Tc = pr_Tc(c), k = pr_kappa(c.omega);
-  const double s = 1.0 + k * (1.0 - std::sqrt(T / Tc));
-  const double p = rho * c.R * T / (1.0 - c.b * rho) -
-                   c.a * s * s * rho * rho /
-                       (1.0 + 2.0 * c.b * rho - c.b * c.b * rho * rho);
-  return 2.0 * (p - rho * (1.0 / 3.0)) / c.G;
-}
-
-const char* check_config(const lbpc_config* c) {
-  if (!c) return "config is NULL";
-  if (c->nx < 4 || c->ny < 4) return "nx and ny must be >= 4";
-  if ((long long)c->nx * (long long)c->ny > (1LL << 31))
-    return "lattice larger than 2^31 nodes";
-  for (int i = 0; i < 4; ++i)
-    if (c->bc[i] < 0 || c->bc[i] > 2) return "bc must be 0, 1 or 2";
-  if ((c->bc[0] == LBPC_BC_PERIODIC) != (c->bc[1] == LBPC_BC_PERIODIC))
-    return "x sides must be both periodic or both not";
-  if ((c->bc[2] == LBPC_BC_PERIODIC) != (c->bc[3] == LBPC_BC_PERIODIC))
-    return "y sides must be both periodic or both not";
-  for (int i = 0; i < 9; ++i)
-    if (!(c->s_f[i] > 0.0 && c->s_f[i] < 2.0) ||
-        !(c->s_g[i] > 0.0 && c->s_g[i] < 2.0))
-      return "relaxation rates must lie in (0, 2)";
-  if (!(c->G < 0.0)) return "G must be negative";
-  if (!(c->a > 0.0 && c->b > 0.0 && c->R > 0.0 && c->cv > 0.0))
-    return "a, b, R and cv must be positive";
-  if (c->lambda_mode != LBPC_LAMBDA_CONST &&
-      c->lambda_mode != LBPC_LAMBDA_RHO_CV_CHI)
-    return "unknown lambda_mode";
-  if (c->thermal_model != LBPC_THERMAL_IMPROVED &&
-      c->thermal_model != LBPC_THERMAL_COMPROMISED)
-    return "unknown thermal_model";
-  if (c->precision < LBPC_FP64 || c->precision > LBPC_FP16_SHIFTED)
-    return "unknown precision";
-  return nullptr;
-}
-
 }  // namespace
 
 struct lbpc_handle {
@@ -173,11 +71,6 @@ StepParams params_now(lbpc_handle* h) {
   return p;
 }
 
-int env_int(const char* name, int dflt) {
-  const char* v = std::getenv(name);
-  return v ? std::atoi(v) : dflt;
-}
-
 }  // namespace
 
 extern "C" {
@@ -213,15 +106,7 @@ lbpc_status lbpc_create(const lbpc_config* cfg, void* dev_workspace,
   h->ws_bytes = workspace_bytes;
   h->L = L;
   StepParams& p = h->base;
-  std::memset(&p, 0, sizeof(p));
-  p.nx = cfg->nx;
-  p.ny = cfg->ny;
-  p.perx = cfg->bc[0] == LBPC_BC_PERIODIC;
-  p.pery = cfg->bc[2] == LBPC_BC_PERIODIC;
-  for (int i = 0; i < 4; ++i) {
-    p.bc[i] = cfg->bc[i];
-    p.T_bc[i] = cfg->T_bc[i];
-  }
+  derive_params(*cfg, p);
   {
     // strip width (threads per block) and rows per block; LBPC_TILE_BW and
     // LBPC_TILE_H override the defaults
@@ -244,37 +129,6 @@ lbpc_status lbpc_create(const lbpc_config* cfg, void* dev_workspace,
     p.nby = (cfg->ny + p.H - 1) / p.H;
     p.xcd_order = env_int("LBPC_XCD_ORDER", 1);
   }
-  p.hot_x0 = cfg->hot_x0;
-  p.hot_x1 = cfg->hot_x1;
-  p.T_hot = cfg->T_hot;
-  p.a = cfg->a;
-  p.b = cfg->b;
-  p.R = cfg->R;
-  p.Tc = pr_Tc(*cfg);
-  p.kappa = pr_kappa(cfg->omega);
-  p.G = cfg->G;
-  p.sigma = cfg->sigma;
-  p.gx = cfg->gx;
-  p.gy = cfg->gy;
-  for (int i = 0; i < 9; ++i) {
-    p.s_f[i] = cfg->s_f[i];
-    p.s_g[i] = cfg->s_g[i];
-  }
-  p.cv = cfg->cv;
-  p.lambda0 = cfg->lambda0;
-  p.chi = cfg->chi;
-  p.k_th = (1.0 / cfg->s_g[3] - 0.5) * (1.0 / 3.0);  // Eq. (A13), c_s^2 = 1/3
-  p.inv_Tc = 1.0 / p.Tc;
-  p.two_over_G = 2.0 / cfg->G;
-  p.inv_cv = 1.0 / cfg->cv;
-  p.lam_over_cv = cfg->lambda0 / cfg->cv;
-  p.sig1 = 12.0 * cfg->sigma * cfg->G * cfg->G / (1.0 / cfg->s_f[1] - 0.5);
-  p.sig2 = 12.0 * cfg->sigma * cfg->G * cfg->G / (1.0 / cfg->s_f[2] - 0.5);
-  p.lambda_mode = cfg->lambda_mode;
-  p.improved = cfg->thermal_model == LBPC_THERMAL_IMPROVED;
-  p.rho_ref = cfg->rho_ref;
-  p.T_ref = cfg->T_ref;
-  p.N = (long long)cfg->nx * cfg->ny;
   *out = h;
   return LBPC_OK;
 }
@@ -287,18 +141,8 @@ lbpc_status lbpc_init_fields(lbpc_handle* h, const double* rho,
     return fail(h, LBPC_ERR_ARG, "field pointer is NULL");
   const lbpc_config& c = h->cfg;
   const size_t N = (size_t)c.nx * c.ny;
-  double sum = 0.0;
-  for (size_t i = 0; i < N; ++i) {
-    if (!(rho[i] > 0.0 && rho[i] < 1.0 / c.b))
-      return fail(h, LBPC_ERR_ARG, "rho outside (0, 1/b)");
-    if (!(T[i] > 0.0) || !std::isfinite(T[i]) || !std::isfinite(ux[i]) ||
-        !std::isfinite(uy[i]))
-      return fail(h, LBPC_ERR_ARG, "T <= 0 or non-finite input");
-    if (!(host_psi2(c, rho[i], T[i]) >= 0.0))
-      return fail(h, LBPC_ERR_ARG, "psi^2 < 0 (p_EOS > rho c_s^2)");
-    sum += rho[i];
-  }
-  h->rho_ave = sum / (double)N;
+  const char* bad = check_fields(c, rho, ux, uy, T, &h->rho_ave);
+  if (bad) return fail(h, LBPC_ERR_ARG, bad);
   double* scr = static_cast<double*>(at(h, h->L.scratch));
   const double* src[4] = {rho, ux, uy, T};
   for (int k = 0; k < 4; ++k)
@@ -471,7 +315,7 @@ lbpc_status lbpc_load_state(lbpc_handle* h, const void* host, size_t bytes) {
 
 void lbpc_destroy(lbpc_handle* h) {
   if (!h) return;
-  (void)hipStreamSynchronize(h->stream);
+  if (h->initialised) (void)hipStreamSynchronize(h->stream);
   delete h;
 }
 

@@ -1,0 +1,504 @@
+// lbpc_batch.cpp -- runtime of the batched form (include/lbpc.h, "batches"):
+// workspace plan for many lattices, the per-lattice parameter table (one
+// entry per lattice and buffer parity), the tile work list, hipGraph capture
+// of one ping-pong period, and the tile-shape autotuner.
+#include <algorithm>
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "lbpc_host.h"
+
+using namespace lbpc_host;
+
+namespace {
+
+thread_local std::string g_berr = "";
+
+struct WorkItem {  // mirrors the device-side work item
+  int c, bx, by, pad;
+};
+
+// candidate tile shapes of the autotuner
+constexpr int CAND_BW[3] = {64, 128, 256};
+constexpr int CAND_H[5] = {16, 24, 32, 48, 64};
+constexpr int MIN_ROWS = 4;
+
+struct CaseLayout {
+  size_t dist[2][2];
+  size_t phi;
+};
+
+struct BatchLayout {
+  size_t table, work, scratch, partial, diag_out;
+  size_t work_capacity;  // items
+  std::vector<CaseLayout> cases;
+  size_t total;
+};
+
+size_t max_items(const lbpc_config* cfgs, int n, int min_rows) {
+  size_t items = 0;
+  const int W = 64 - 2 * lbpc::HALO;
+  for (int c = 0; c < n; ++c)
+    items += (size_t)((cfgs[c].nx + W - 1) / W) *
+             (size_t)((cfgs[c].ny + min_rows - 1) / min_rows);
+  return items;
+}
+
+BatchLayout plan_batch(const lbpc_config* cfgs, int n) {
+  BatchLayout L;
+  size_t off = 0;
+  L.table = off;
+  off += align_up(2 * (size_t)n * sizeof(StepParams));
+  L.work_capacity = max_items(cfgs, n, MIN_ROWS);
+  L.work = off;
+  off += align_up(L.work_capacity * sizeof(WorkItem));
+  size_t maxN = 0;
+  for (int c = 0; c < n; ++c)
+    maxN = std::max(maxN, (size_t)cfgs[c].nx * (size_t)cfgs[c].ny);
+  L.scratch = off;
+  off += align_up(5 * maxN * sizeof(double));
+  L.partial = off;
+  off += align_up((size_t)lbpc::diag_blocks((long long)maxN) * 8 *
+                  sizeof(double));
+  L.diag_out = off;
+  off += align_up(8 * sizeof(double));
+  L.cases.resize(n);
+  for (int c = 0; c < n; ++c) {
+    const size_t N = (size_t)cfgs[c].nx * cfgs[c].ny;
+    const size_t d = align_up(9 * N * store_bytes(cfgs[c].precision));
+    for (int b = 0; b < 2; ++b)
+      for (int k = 0; k < 2; ++k) {
+        L.cases[c].dist[b][k] = off;
+        off += d;
+      }
+    L.cases[c].phi = off;
+    off += align_up(N * compute_bytes(cfgs[c].precision));
+  }
+  L.total = off;
+  return L;
+}
+
+const char* check_batch(const lbpc_config* cfgs, int n) {
+  if (!cfgs || n < 1) return "need at least one configuration";
+  for (int c = 0; c < n; ++c) {
+    const char* bad = check_config(&cfgs[c]);
+    if (bad) return bad;
+    if (cfgs[c].precision != cfgs[0].precision)
+      return "all lattices of a batch share one precision";
+    if (cfgs[c].flags != 0) return "flags are test hooks of the oracle only";
+  }
+  return nullptr;
+}
+
+}  // namespace
+
+struct lbpc_batch {
+  std::vector<lbpc_config> cfgs;
+  int n;
+  int prec;
+  hipStream_t stream;
+  char* ws;
+  BatchLayout L;
+  std::vector<StepParams> base;        // per-lattice constants
+  std::vector<StepParams> table_host;  // [2n] as uploaded
+  std::vector<WorkItem> work_host;
+  std::vector<int> initialised;
+  std::vector<double> rho_ave;
+  int cur, fresh, phi_valid;
+  int64_t step;
+  int bw, rows, nwork, grid;
+  int table_fresh, table_phi_valid;  // flags the uploaded table carries
+  hipGraphExec_t graph[2];
+  int use_graph;
+  std::string err;
+};
+
+namespace {
+
+lbpc_status bfail(lbpc_batch* b, lbpc_status st, const std::string& msg) {
+  if (b)
+    b->err = msg;
+  else
+    g_berr = msg;
+  return st;
+}
+
+#define BHIP(b, expr, what)                                                 \
+  do {                                                                      \
+    hipError_t e_ = (expr);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      return bfail(b, LBPC_ERR_HIP, std::string(what) + ": " +              \
+                                        hipGetErrorString(e_));             \
+  } while (0)
+
+void* at(lbpc_batch* b, size_t off) { return b->ws + off; }
+
+// parameters of lattice c when buffer `par` holds its state
+StepParams case_params(lbpc_batch* b, int c, int par) {
+  StepParams p = b->base[c];
+  const CaseLayout& cl = b->L.cases[c];
+  p.fin = at(b, cl.dist[par][0]);
+  p.gin = at(b, cl.dist[par][1]);
+  p.fout = at(b, cl.dist[1 - par][0]);
+  p.gout = at(b, cl.dist[1 - par][1]);
+  p.phi = at(b, cl.phi);
+  p.fresh = b->fresh;
+  p.phi_valid = b->phi_valid;
+  p.rho_ave = b->rho_ave[c];
+  p.bw = b->bw;
+  p.W = b->bw - 2 * lbpc::HALO;
+  p.H = b->rows;
+  p.nbx = (p.nx + p.W - 1) / p.W;
+  p.nby = (p.ny + p.H - 1) / p.H;
+  p.xcd_order = 0;
+  return p;
+}
+
+lbpc_status upload_table(lbpc_batch* b) {
+  b->table_host.resize(2 * (size_t)b->n);
+  for (int c = 0; c < b->n; ++c)
+    for (int par = 0; par < 2; ++par)
+      b->table_host[2 * c + par] = case_params(b, c, par);
+  BHIP(b,
+       hipMemcpyAsync(at(b, b->L.table), b->table_host.data(),
+                      b->table_host.size() * sizeof(StepParams),
+                      hipMemcpyHostToDevice, b->stream),
+       "parameter table upload");
+  BHIP(b, hipStreamSynchronize(b->stream), "synchronise");
+  b->table_fresh = b->fresh;
+  b->table_phi_valid = b->phi_valid;
+  return LBPC_OK;
+}
+
+void drop_graphs(lbpc_batch* b) {
+  for (int k = 0; k < 2; ++k)
+    if (b->graph[k]) {
+      (void)hipGraphExecDestroy(b->graph[k]);
+      b->graph[k] = nullptr;
+    }
+}
+
+// work list for the current tile shape: tiles of the largest lattices first
+lbpc_status build_work(lbpc_batch* b) {
+  const int W = b->bw - 2 * lbpc::HALO;
+  std::vector<int> order(b->n);
+  for (int c = 0; c < b->n; ++c) order[c] = c;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return (long long)b->cfgs[x].nx * b->cfgs[x].ny >
+           (long long)b->cfgs[y].nx * b->cfgs[y].ny;
+  });
+  b->work_host.clear();
+  for (int c : order) {
+    const int nbx = (b->cfgs[c].nx + W - 1) / W;
+    const int nby = (b->cfgs[c].ny + b->rows - 1) / b->rows;
+    for (int by = 0; by < nby; ++by)
+      for (int bx = 0; bx < nbx; ++bx) b->work_host.push_back({c, bx, by, 0});
+  }
+  if (b->work_host.size() > b->L.work_capacity)
+    return bfail(b, LBPC_ERR_OOM, "work list exceeds its reserved space");
+  b->nwork = (int)b->work_host.size();
+  BHIP(b,
+       hipMemcpyAsync(at(b, b->L.work), b->work_host.data(),
+                      b->work_host.size() * sizeof(WorkItem),
+                      hipMemcpyHostToDevice, b->stream),
+       "work list upload");
+  // one persistent block per resident slot: CUs x blocks per CU (registers
+  // allow 2 waves per SIMD in FP64, 3 otherwise; 4 SIMDs per CU)
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                dev);
+  const int waves = b->prec == LBPC_FP64 ? 2 : 3;
+  const int per_cu = std::max(1, 4 * waves / (b->bw / 64));
+  b->grid = std::max(1, std::min(b->nwork, cus * per_cu));
+  drop_graphs(b);
+  return upload_table(b);
+}
+
+lbpc_status launch(lbpc_batch* b, int parity) {
+  BHIP(b,
+       lbpc::launch_step_batch(
+           static_cast<const StepParams*>(at(b, b->L.table)),
+           at(b, b->L.work), b->nwork, parity, b->grid, b->prec, b->bw,
+           b->stream),
+       "batched step kernel");
+  return LBPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbpc_status lbpc_batch_workspace_bytes(const lbpc_config* cfgs, int32_t n,
+                                       size_t* bytes) {
+  const char* bad = check_batch(cfgs, n);
+  if (bad) return bfail(nullptr, LBPC_ERR_ARG, bad);
+  if (!bytes) return bfail(nullptr, LBPC_ERR_ARG, "bytes is NULL");
+  *bytes = plan_batch(cfgs, n).total;
+  return LBPC_OK;
+}
+
+lbpc_status lbpc_batch_create(const lbpc_config* cfgs, int32_t n,
+                              void* dev_workspace, size_t workspace_bytes,
+                              void* hip_stream, lbpc_batch** out) {
+  if (!out) return bfail(nullptr, LBPC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  const char* bad = check_batch(cfgs, n);
+  if (bad) return bfail(nullptr, LBPC_ERR_ARG, bad);
+  BatchLayout L = plan_batch(cfgs, n);
+  if (!dev_workspace || workspace_bytes < L.total)
+    return bfail(nullptr, LBPC_ERR_OOM, "workspace missing or too small");
+  if (reinterpret_cast<uintptr_t>(dev_workspace) % ALIGN != 0)
+    return bfail(nullptr, LBPC_ERR_ARG, "workspace must be 256-byte aligned");
+  lbpc_batch* b = new (std::nothrow) lbpc_batch();
+  if (!b) return bfail(nullptr, LBPC_ERR_OOM, "host allocation failed");
+  b->cfgs.assign(cfgs, cfgs + n);
+  b->n = n;
+  b->prec = cfgs[0].precision;
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  b->ws = static_cast<char*>(dev_workspace);
+  b->L = L;
+  b->base.resize(n);
+  for (int c = 0; c < n; ++c) derive_params(cfgs[c], b->base[c]);
+  b->initialised.assign(n, 0);
+  b->rho_ave.assign(n, 0.0);
+  b->cur = 0;
+  b->fresh = 1;
+  b->phi_valid = 0;
+  b->step = 0;
+  b->bw = env_int("LBPC_TILE_BW", 256);
+  if (b->bw != 64 && b->bw != 128 && b->bw != 256) b->bw = 256;
+  b->rows = std::max(MIN_ROWS, env_int("LBPC_TILE_H", 32));
+  b->graph[0] = b->graph[1] = nullptr;
+  // graph replay needs a capturable (non-NULL) stream
+  b->use_graph = b->stream != nullptr && env_int("LBPC_BATCH_GRAPH", 1) != 0;
+  lbpc_status st = build_work(b);
+  if (st != LBPC_OK) {
+    g_berr = b->err;
+    delete b;
+    return st;
+  }
+  *out = b;
+  return LBPC_OK;
+}
+
+lbpc_status lbpc_batch_init_fields(lbpc_batch* b, int32_t c,
+                                   const double* rho, const double* ux,
+                                   const double* uy, const double* T) {
+  if (!b) return bfail(nullptr, LBPC_ERR_ARG, "batch is NULL");
+  if (c < 0 || c >= b->n) return bfail(b, LBPC_ERR_ARG, "lattice index");
+  if (!rho || !ux || !uy || !T)
+    return bfail(b, LBPC_ERR_ARG, "field pointer is NULL");
+  if (b->step != 0)
+    return bfail(b, LBPC_ERR_STATE, "initial fields after the first step");
+  const char* bad = check_fields(b->cfgs[c], rho, ux, uy, T, &b->rho_ave[c]);
+  if (bad) return bfail(b, LBPC_ERR_ARG, bad);
+  const size_t N = (size_t)b->cfgs[c].nx * b->cfgs[c].ny;
+  double* scr = static_cast<double*>(at(b, b->L.scratch));
+  const double* src[4] = {rho, ux, uy, T};
+  for (int k = 0; k < 4; ++k)
+    BHIP(b,
+         hipMemcpyAsync(scr + k * N, src[k], N * sizeof(double),
+                        hipMemcpyHostToDevice, b->stream),
+         "copy of the initial fields");
+  StepParams p = case_params(b, c, b->cur);
+  BHIP(b, lbpc::launch_init(p, b->prec, scr, b->stream), "init kernel");
+  BHIP(b, hipStreamSynchronize(b->stream), "synchronise");
+  b->initialised[c] = 1;
+  b->fresh = 1;
+  b->phi_valid = 0;
+  return upload_table(b);
+}
+
+lbpc_status lbpc_batch_set_tiles(lbpc_batch* b, int32_t block_width,
+                                 int32_t rows) {
+  if (!b) return bfail(nullptr, LBPC_ERR_ARG, "batch is NULL");
+  if (block_width != 64 && block_width != 128 && block_width != 256)
+    return bfail(b, LBPC_ERR_ARG, "block width must be 64, 128 or 256");
+  if (rows < MIN_ROWS) return bfail(b, LBPC_ERR_ARG, "rows must be >= 4");
+  BHIP(b, hipStreamSynchronize(b->stream), "synchronise");
+  b->bw = block_width;
+  b->rows = rows;
+  return build_work(b);
+}
+
+lbpc_status lbpc_batch_autotune(lbpc_batch* b, int32_t steps,
+                                int32_t* block_width, int32_t* rows,
+                                double* ms_per_step) {
+  if (!b) return bfail(nullptr, LBPC_ERR_ARG, "batch is NULL");
+  if (steps < 1) return bfail(b, LBPC_ERR_ARG, "steps < 1");
+  for (int c = 0; c < b->n; ++c)
+    if (!b->initialised[c])
+      return bfail(b, LBPC_ERR_STATE, "autotune before every lattice is set");
+  // the initialised state is read in place (fresh) and phi_prev is unused
+  // until the first real step, so timing launches leave the state unchanged
+  if (b->step != 0 || !b->fresh || b->phi_valid)
+    return bfail(b, LBPC_ERR_STATE, "autotune only before the first step");
+  hipEvent_t e0, e1;
+  BHIP(b, hipEventCreate(&e0), "event");
+  BHIP(b, hipEventCreate(&e1), "event");
+  float best = 1e30f;
+  int best_bw = b->bw, best_rows = b->rows;
+  for (int bw : CAND_BW)
+    for (int h : CAND_H) {
+      b->bw = bw;
+      b->rows = h;
+      lbpc_status st = build_work(b);
+      if (st != LBPC_OK) return st;
+      st = launch(b, b->cur);  // warm-up
+      if (st != LBPC_OK) return st;
+      BHIP(b, hipEventRecord(e0, b->stream), "event");
+      for (int s = 0; s < steps; ++s) {
+        st = launch(b, b->cur);
+        if (st != LBPC_OK) return st;
+      }
+      BHIP(b, hipEventRecord(e1, b->stream), "event");
+      BHIP(b, hipEventSynchronize(e1), "event");
+      float ms = 0.f;
+      BHIP(b, hipEventElapsedTime(&ms, e0, e1), "event");
+      if (ms < best) {
+        best = ms;
+        best_bw = bw;
+        best_rows = h;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->bw = best_bw;
+  b->rows = best_rows;
+  lbpc_status st = build_work(b);
+  if (st != LBPC_OK) return st;
+  if (block_width) *block_width = best_bw;
+  if (rows) *rows = best_rows;
+  if (ms_per_step) *ms_per_step = best / steps;
+  return LBPC_OK;
+}
+
+lbpc_status lbpc_batch_step(lbpc_batch* b, int64_t n) {
+  if (!b) return bfail(nullptr, LBPC_ERR_ARG, "batch is NULL");
+  if (n < 0) return bfail(b, LBPC_ERR_ARG, "n < 0");
+  for (int c = 0; c < b->n; ++c)
+    if (!b->initialised[c])
+      return bfail(b, LBPC_ERR_STATE, "step before every lattice is set");
+  while (n > 0) {
+    const bool steady = !b->fresh && b->phi_valid;
+    if (steady && (b->table_fresh || !b->table_phi_valid)) {
+      lbpc_status st = upload_table(b);
+      if (st != LBPC_OK) return st;
+    }
+    if (steady && b->use_graph && n >= 2) {
+      hipGraphExec_t& g = b->graph[b->cur];
+      if (!g) {
+        hipGraph_t graph;
+        BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal),
+             "graph capture");
+        lbpc_status st = launch(b, b->cur);
+        lbpc_status st2 = st == LBPC_OK ? launch(b, 1 - b->cur) : st;
+        hipError_t e = hipStreamEndCapture(b->stream, &graph);
+        if (st2 != LBPC_OK) return st2;
+        BHIP(b, e, "graph capture");
+        BHIP(b, hipGraphInstantiate(&g, graph, nullptr, nullptr, 0),
+             "graph instantiate");
+        (void)hipGraphDestroy(graph);
+      }
+      const int64_t pairs = n / 2;
+      for (int64_t k = 0; k < pairs; ++k)
+        BHIP(b, hipGraphLaunch(g, b->stream), "graph launch");
+      b->step += 2 * pairs;
+      n -= 2 * pairs;
+      continue;
+    }
+    if (!steady && (b->table_fresh != b->fresh ||
+                    b->table_phi_valid != b->phi_valid)) {
+      lbpc_status st = upload_table(b);
+      if (st != LBPC_OK) return st;
+    }
+    lbpc_status st = launch(b, b->cur);
+    if (st != LBPC_OK) return st;
+    b->cur = 1 - b->cur;
+    b->fresh = 0;
+    b->phi_valid = 1;
+    b->step += 1;
+    n -= 1;
+  }
+  return LBPC_OK;
+}
+
+lbpc_status lbpc_batch_get_rho_u_T(lbpc_batch* b, int32_t c, double* rho,
+                                   double* ux, double* uy, double* T) {
+  if (!b) return bfail(nullptr, LBPC_ERR_ARG, "batch is NULL");
+  if (c < 0 || c >= b->n) return bfail(b, LBPC_ERR_ARG, "lattice index");
+  if (!b->initialised[c]) return bfail(b, LBPC_ERR_STATE, "not initialised");
+  const size_t N = (size_t)b->cfgs[c].nx * b->cfgs[c].ny;
+  double* scr = static_cast<double*>(at(b, b->L.scratch));
+  StepParams p = case_params(b, c, b->cur);
+  BHIP(b, lbpc::launch_macro(p, b->prec, scr, b->stream), "macro kernels");
+  double* dst[4] = {rho, ux, uy, T};
+  for (int k = 0; k < 4; ++k)
+    if (dst[k])
+      BHIP(b,
+           hipMemcpyAsync(dst[k], scr + k * N, N * sizeof(double),
+                          hipMemcpyDeviceToHost, b->stream),
+           "copy of the fields");
+  BHIP(b, hipStreamSynchronize(b->stream), "synchronise");
+  for (int k = 0; k < 4; ++k)
+    if (dst[k])
+      for (size_t i = 0; i < N; ++i)
+        if (!std::isfinite(dst[k][i]))
+          return bfail(b, LBPC_ERR_NUMERIC, "non-finite field value");
+  return LBPC_OK;
+}
+
+lbpc_status lbpc_batch_get_diag(lbpc_batch* b, int32_t c, lbpc_diag* out) {
+  if (!b) return bfail(nullptr, LBPC_ERR_ARG, "batch is NULL");
+  if (c < 0 || c >= b->n || !out) return bfail(b, LBPC_ERR_ARG, "argument");
+  if (!b->initialised[c]) return bfail(b, LBPC_ERR_STATE, "not initialised");
+  double* scr = static_cast<double*>(at(b, b->L.scratch));
+  StepParams p = case_params(b, c, b->cur);
+  BHIP(b, lbpc::launch_macro(p, b->prec, scr, b->stream), "macro kernels");
+  double* dout = static_cast<double*>(at(b, b->L.diag_out));
+  BHIP(b,
+       lbpc::launch_diag(p, scr, b->cfgs[c].rho_v, b->cfgs[c].rho_l,
+                         static_cast<double*>(at(b, b->L.partial)), dout,
+                         b->stream),
+       "diagnostic kernels");
+  double r[8];
+  BHIP(b,
+       hipMemcpyAsync(r, dout, sizeof(r), hipMemcpyDeviceToHost, b->stream),
+       "copy of the diagnostics");
+  BHIP(b, hipStreamSynchronize(b->stream), "synchronise");
+  std::memset(out, 0, sizeof(*out));
+  out->mass = r[0];
+  out->sum_T = r[1];
+  out->sum_rhocvT = r[2];
+  out->liquid_area = r[3];
+  out->radius = std::sqrt(r[3] / M_PI);
+  out->radius_count = std::sqrt(r[4] / M_PI);
+  out->max_speed = r[5];
+  out->nonfinite = r[6] != 0.0 || !std::isfinite(r[0]) || !std::isfinite(r[1]);
+  out->step = b->step;
+  return LBPC_OK;
+}
+
+lbpc_status lbpc_batch_nodes(const lbpc_batch* b, int64_t* nodes) {
+  if (!b || !nodes) return bfail(nullptr, LBPC_ERR_ARG, "NULL argument");
+  int64_t s = 0;
+  for (const auto& c : b->cfgs) s += (int64_t)c.nx * c.ny;
+  *nodes = s;
+  return LBPC_OK;
+}
+
+void lbpc_batch_destroy(lbpc_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  drop_graphs(b);
+  delete b;
+}
+
+const char* lbpc_batch_last_error(const lbpc_batch* b) {
+  return b ? b->err.c_str() : g_berr.c_str();
+}
+
+}  // extern "C"

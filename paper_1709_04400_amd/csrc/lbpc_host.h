@@ -1,0 +1,193 @@
+// lbpc_host.h -- host-side pieces shared by the single-lattice and the
+// batched runtimes: launcher declarations, configuration checks, the derived
+// constants of a lattice and the Peng-Robinson checks of the inputs.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "../../include/lbpc.h"
+#include "lbpc_device.h"
+
+namespace lbpc {
+hipError_t launch_step(const StepParams& p, int prec, hipStream_t s);
+hipError_t launch_init(const StepParams& p, int prec, const double* in,
+                       hipStream_t s);
+hipError_t launch_macro(const StepParams& p, int prec, double* io,
+                        hipStream_t s);
+hipError_t launch_diag(const StepParams& p, const double* io, double rho_v,
+                       double rho_l, double* partial, double* out,
+                       hipStream_t s);
+hipError_t launch_canon(const StepParams& p, int prec, int which, double* out,
+                        hipStream_t s);
+hipError_t launch_load(const StepParams& p, int prec, int which,
+                       const double* in, hipStream_t s);
+hipError_t launch_phi_out(const StepParams& p, int prec, double* out,
+                          hipStream_t s);
+hipError_t launch_phi_in(const StepParams& p, int prec, const double* in,
+                         hipStream_t s);
+int diag_blocks(long long N);
+hipError_t launch_step_batch(const StepParams* table, const void* work,
+                             int nwork, int parity, int grid, int prec,
+                             int bw, hipStream_t s);
+int work_item_bytes();
+}  // namespace lbpc
+
+using lbpc::StepParams;
+
+namespace lbpc_host {
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+inline size_t store_bytes(int prec) {
+  return prec == LBPC_FP64 ? 8 : (prec == LBPC_FP16_SHIFTED ? 2 : 4);
+}
+inline size_t compute_bytes(int prec) { return prec == LBPC_FP64 ? 8 : 4; }
+
+struct Layout {
+  size_t dist[2][2];  // offsets of f / g of buffer 0 / 1
+  size_t phi, scratch, partial, diag_out;
+  size_t total;
+};
+
+inline Layout plan(const lbpc_config& c) {
+  Layout L;
+  const size_t N = (size_t)c.nx * (size_t)c.ny;
+  const size_t dbytes = align_up(9 * N * store_bytes(c.precision));
+  size_t off = 0;
+  for (int b = 0; b < 2; ++b)
+    for (int k = 0; k < 2; ++k) {
+      L.dist[b][k] = off;
+      off += dbytes;
+    }
+  L.phi = off;
+  off += align_up(N * compute_bytes(c.precision));
+  L.scratch = off;
+  off += align_up(5 * N * sizeof(double));
+  L.partial = off;
+  off += align_up((size_t)lbpc::diag_blocks((long long)N) * 8 * sizeof(double));
+  L.diag_out = off;
+  off += align_up(8 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+inline double pr_Tc(const lbpc_config& c) {
+  return 0.0778 * c.a / (0.45724 * c.b * c.R);
+}
+inline double pr_kappa(double w) { return 0.37464 + 1.54226 * w - 0.26992 * w * w; }
+
+inline double host_psi2(const lbpc_config& c, double rho, double T) {
+  const double Tc = pr_Tc(c), k = pr_kappa(c.omega);
+  const double s = 1.0 + k * (1.0 - std::sqrt(T / Tc));
+  const double p = rho * c.R * T / (1.0 - c.b * rho) -
+                   c.a * s * s * rho * rho /
+                       (1.0 + 2.0 * c.b * rho - c.b * c.b * rho * rho);
+  return 2.0 * (p - rho * (1.0 / 3.0)) / c.G;
+}
+
+inline const char* check_config(const lbpc_config* c) {
+  if (!c) return "config is NULL";
+  if (c->nx < 4 || c->ny < 4) return "nx and ny must be >= 4";
+  if ((long long)c->nx * (long long)c->ny > (1LL << 31))
+    return "lattice larger than 2^31 nodes";
+  for (int i = 0; i < 4; ++i)
+    if (c->bc[i] < 0 || c->bc[i] > 2) return "bc must be 0, 1 or 2";
+  if ((c->bc[0] == LBPC_BC_PERIODIC) != (c->bc[1] == LBPC_BC_PERIODIC))
+    return "x sides must be both periodic or both not";
+  if ((c->bc[2] == LBPC_BC_PERIODIC) != (c->bc[3] == LBPC_BC_PERIODIC))
+    return "y sides must be both periodic or both not";
+  for (int i = 0; i < 9; ++i)
+    if (!(c->s_f[i] > 0.0 && c->s_f[i] < 2.0) ||
+        !(c->s_g[i] > 0.0 && c->s_g[i] < 2.0))
+      return "relaxation rates must lie in (0, 2)";
+  if (!(c->G < 0.0)) return "G must be negative";
+  if (!(c->a > 0.0 && c->b > 0.0 && c->R > 0.0 && c->cv > 0.0))
+    return "a, b, R and cv must be positive";
+  if (c->lambda_mode != LBPC_LAMBDA_CONST &&
+      c->lambda_mode != LBPC_LAMBDA_RHO_CV_CHI)
+    return "unknown lambda_mode";
+  if (c->thermal_model != LBPC_THERMAL_IMPROVED &&
+      c->thermal_model != LBPC_THERMAL_COMPROMISED)
+    return "unknown thermal_model";
+  if (c->precision < LBPC_FP64 || c->precision > LBPC_FP16_SHIFTED)
+    return "unknown precision";
+  return nullptr;
+}
+
+// Per-lattice constants of the step kernels (buffers, state flags and the
+// tile shape are filled in by the caller).
+inline void derive_params(const lbpc_config& c, StepParams& p) {
+  std::memset(&p, 0, sizeof(p));
+  p.nx = c.nx;
+  p.ny = c.ny;
+  p.perx = c.bc[0] == LBPC_BC_PERIODIC;
+  p.pery = c.bc[2] == LBPC_BC_PERIODIC;
+  for (int i = 0; i < 4; ++i) {
+    p.bc[i] = c.bc[i];
+    p.T_bc[i] = c.T_bc[i];
+  }
+  p.hot_x0 = c.hot_x0;
+  p.hot_x1 = c.hot_x1;
+  p.T_hot = c.T_hot;
+  p.a = c.a;
+  p.b = c.b;
+  p.R = c.R;
+  p.Tc = pr_Tc(c);
+  p.kappa = pr_kappa(c.omega);
+  p.G = c.G;
+  p.sigma = c.sigma;
+  p.gx = c.gx;
+  p.gy = c.gy;
+  for (int i = 0; i < 9; ++i) {
+    p.s_f[i] = c.s_f[i];
+    p.s_g[i] = c.s_g[i];
+  }
+  p.cv = c.cv;
+  p.lambda0 = c.lambda0;
+  p.chi = c.chi;
+  p.k_th = (1.0 / c.s_g[3] - 0.5) * (1.0 / 3.0);  // Eq. (A13), c_s^2 = 1/3
+  p.inv_Tc = 1.0 / p.Tc;
+  p.two_over_G = 2.0 / c.G;
+  p.inv_cv = 1.0 / c.cv;
+  p.lam_over_cv = c.lambda0 / c.cv;
+  p.sig1 = 12.0 * c.sigma * c.G * c.G / (1.0 / c.s_f[1] - 0.5);
+  p.sig2 = 12.0 * c.sigma * c.G * c.G / (1.0 / c.s_f[2] - 0.5);
+  p.lambda_mode = c.lambda_mode;
+  p.improved = c.thermal_model == LBPC_THERMAL_IMPROVED;
+  p.rho_ref = c.rho_ref;
+  p.T_ref = c.T_ref;
+  p.N = (long long)c.nx * c.ny;
+}
+
+// Host checks of initial fields (same rules as the library documents):
+// returns nullptr when valid, and the mean density in *rho_ave.
+inline const char* check_fields(const lbpc_config& c, const double* rho,
+                                const double* ux, const double* uy,
+                                const double* T, double* rho_ave) {
+  const size_t N = (size_t)c.nx * c.ny;
+  double sum = 0.0;
+  for (size_t i = 0; i < N; ++i) {
+    if (!(rho[i] > 0.0 && rho[i] < 1.0 / c.b)) return "rho outside (0, 1/b)";
+    if (!(T[i] > 0.0) || !std::isfinite(T[i]) || !std::isfinite(ux[i]) ||
+        !std::isfinite(uy[i]))
+      return "T <= 0 or non-finite input";
+    if (!(host_psi2(c, rho[i], T[i]) >= 0.0))
+      return "psi^2 < 0 (p_EOS > rho c_s^2)";
+    sum += rho[i];
+  }
+  *rho_ave = sum / (double)N;
+  return nullptr;
+}
+
+inline int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return v ? std::atoi(v) : dflt;
+}
+
+}  // namespace lbpc_host
+

@@ -53,10 +53,10 @@ __device__ __forceinline__ void block_tile(const StepParams& p, int& bx,
 // queues of pulled values in 64-bit registers
 template <int P> struct StepOcc { static constexpr int waves = P == 0 ? 2 : 3; };
 
+// One tile: strip bx (W columns + halo), row run by (H rows), of the lattice
+// described by p.
 template <int P, bool GEN, int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((
-    amdgpu_waves_per_eu(StepOcc<P>::waves, StepOcc<P>::waves))) void
-k_step(StepParams p) {
+__device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
   using Tr = Prec<P>;
   using S = typename Tr::S;
   using C = typename Tr::C;
@@ -70,8 +70,6 @@ k_step(StepParams p) {
   const int t = threadIdx.x;
   const int nx = p.nx, ny = p.ny;
   const long long N = p.N;
-  int bx, by;
-  block_tile(p, bx, by);
   const int X0 = bx * p.W, X1 = min(X0 + p.W, nx);
   const int Y0 = by * p.H, Y1 = min(Y0 + p.H, ny);
   const int c = X0 - HALO + t;  // unwrapped column of this thread
@@ -404,6 +402,37 @@ k_step(StepParams p) {
   }
 }
 
+template <int P, bool GEN, int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((
+    amdgpu_waves_per_eu(StepOcc<P>::waves, StepOcc<P>::waves))) void
+k_step(StepParams p) {
+  int bx, by;
+  block_tile(p, bx, by);
+  step_tile<P, GEN, BLOCK>(p, bx, by);
+}
+
+// Batched form: many independent lattices, one persistent launch per step.
+// `table` holds each case's parameters for both buffer parities; `work`
+// lists (case, bx, by) tiles, costliest first; every block walks the list
+// with a stride of the grid size, so each tile is done exactly once and
+// every block leaves when the list ends.
+struct WorkItem {
+  int c, bx, by, pad;
+};
+
+template <int P, int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((
+    amdgpu_waves_per_eu(StepOcc<P>::waves, StepOcc<P>::waves))) void
+k_step_batch(const StepParams* __restrict__ table,
+             const WorkItem* __restrict__ work, int nwork, int parity) {
+  for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+    const WorkItem it = work[w];
+    const StepParams& p = table[2 * it.c + parity];
+    step_tile<P, true, BLOCK>(p, it.bx, it.by);
+    __syncthreads();  // the LDS rings are reused by the next tile
+  }
+}
+
 // host-side launcher: one instantiation per storage precision and boundary
 // mode (GEN = some side is not periodic)
 hipError_t launch_step(const StepParams& p, int prec, hipStream_t s) {
@@ -433,5 +462,34 @@ hipError_t launch_step(const StepParams& p, int prec, hipStream_t s) {
 #undef LBPC_LAUNCH_BW
   return hipGetLastError();
 }
+
+hipError_t launch_step_batch(const StepParams* table, const void* work,
+                             int nwork, int parity, int grid, int prec,
+                             int bw, hipStream_t s) {
+  const WorkItem* wk = static_cast<const WorkItem*>(work);
+#define LBPC_BLAUNCH_BW(PR, BW)                                               \
+  hipLaunchKernelGGL((k_step_batch<PR, BW>), dim3(grid), dim3(BW), 0, s,    \
+                     table, wk, nwork, parity);
+#define LBPC_BLAUNCH(PR)                                                      \
+  if (bw == 64) {                                                             \
+    LBPC_BLAUNCH_BW(PR, 64)                                                   \
+  } else if (bw == 128) {                                                     \
+    LBPC_BLAUNCH_BW(PR, 128)                                                  \
+  } else {                                                                    \
+    LBPC_BLAUNCH_BW(PR, 256)                                                  \
+  }
+  switch (prec) {
+    case 0: LBPC_BLAUNCH(0); break;
+    case 1: LBPC_BLAUNCH(1); break;
+    case 2: LBPC_BLAUNCH(2); break;
+    case 3: LBPC_BLAUNCH(3); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef LBPC_BLAUNCH
+#undef LBPC_BLAUNCH_BW
+  return hipGetLastError();
+}
+
+int work_item_bytes() { return (int)sizeof(WorkItem); }
 
 }  // namespace lbpc

@@ -24,6 +24,10 @@ EXPORTS = (
     "lbpc_workspace_bytes", "lbpc_create", "lbpc_init_fields", "lbpc_step",
     "lbpc_get_rho_u_T", "lbpc_get_diag", "lbpc_state_bytes",
     "lbpc_save_state", "lbpc_load_state", "lbpc_destroy", "lbpc_last_error",
+    "lbpc_batch_workspace_bytes", "lbpc_batch_create",
+    "lbpc_batch_init_fields", "lbpc_batch_set_tiles", "lbpc_batch_autotune",
+    "lbpc_batch_step", "lbpc_batch_get_rho_u_T", "lbpc_batch_get_diag",
+    "lbpc_batch_nodes", "lbpc_batch_destroy", "lbpc_batch_last_error",
 )
 
 
@@ -95,8 +99,27 @@ def lib():
         L.lbpc_destroy.restype = None
         L.lbpc_last_error.argtypes = [vp]
         L.lbpc_last_error.restype = ctypes.c_char_p
+        i32, i64p = ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)
+        L.lbpc_batch_workspace_bytes.argtypes = [
+            ctypes.POINTER(Config), i32, ctypes.POINTER(ctypes.c_size_t)]
+        L.lbpc_batch_create.argtypes = [ctypes.POINTER(Config), i32, vp,
+                                        ctypes.c_size_t, vp,
+                                        ctypes.POINTER(vp)]
+        L.lbpc_batch_init_fields.argtypes = [vp, i32, dp, dp, dp, dp]
+        L.lbpc_batch_set_tiles.argtypes = [vp, i32, i32]
+        L.lbpc_batch_autotune.argtypes = [vp, i32, ctypes.POINTER(i32),
+                                          ctypes.POINTER(i32), dp]
+        L.lbpc_batch_step.argtypes = [vp, ctypes.c_int64]
+        L.lbpc_batch_get_rho_u_T.argtypes = [vp, i32, dp, dp, dp, dp]
+        L.lbpc_batch_get_diag.argtypes = [vp, i32, ctypes.POINTER(Diag)]
+        L.lbpc_batch_nodes.argtypes = [vp, i64p]
+        L.lbpc_batch_destroy.argtypes = [vp]
+        L.lbpc_batch_destroy.restype = None
+        L.lbpc_batch_last_error.argtypes = [vp]
+        L.lbpc_batch_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
-            if name not in ("lbpc_destroy", "lbpc_last_error"):
+            if name not in ("lbpc_destroy", "lbpc_last_error",
+                            "lbpc_batch_destroy", "lbpc_batch_last_error"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -228,6 +251,111 @@ class Simulation:
     def close(self):
         if getattr(self, "h", None):
             lbpc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------- batches ---
+
+def _bcheck(st, b=None):
+    if st != OK:
+        msg = lib().lbpc_batch_last_error(b)
+        raise LbpcError(st, msg.decode() if msg else "")
+
+
+def _config_array(cfgs):
+    arr = (Config * len(cfgs))()
+    for i, d in enumerate(cfgs):
+        arr[i] = make_config(d)
+    return arr
+
+
+def lbpc_batch_workspace_bytes(cfgs) -> int:
+    arr = _config_array(cfgs)
+    out = ctypes.c_size_t()
+    _bcheck(lib().lbpc_batch_workspace_bytes(arr, len(cfgs),
+                                             ctypes.byref(out)))
+    return out.value
+
+
+class Batch:
+    """Many independent lattices stepped by one persistent launch per step.
+
+    Uses its own (default-priority) torch stream, so that steady-state steps
+    are replayed from a captured hipGraph."""
+
+    def __init__(self, cfgs, device: str = "cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the lbpc library needs one")
+        self.cfgs = [dict(c) for c in cfgs]
+        self.device = torch.device(device)
+        arr = _config_array(self.cfgs)
+        nbytes = lbpc_batch_workspace_bytes(self.cfgs)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8,
+                              device=self.device)
+        ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        self.stream = stream if stream is not None else \
+            torch.cuda.Stream(self.device)
+        h = ctypes.c_void_p()
+        _bcheck(lib().lbpc_batch_create(arr, len(self.cfgs),
+                                        ctypes.c_void_p(ptr), nbytes,
+                                        ctypes.c_void_p(
+                                            self.stream.cuda_stream),
+                                        ctypes.byref(h)))
+        self.h = h
+
+    def __len__(self):
+        return len(self.cfgs)
+
+    def init_fields(self, c, rho, ux, uy, T):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64)
+                for a in (rho, ux, uy, T)]
+        _bcheck(lib().lbpc_batch_init_fields(self.h, int(c), *map(_dp, arrs)),
+                self.h)
+
+    def set_tiles(self, block_width, rows):
+        _bcheck(lib().lbpc_batch_set_tiles(self.h, int(block_width),
+                                           int(rows)), self.h)
+
+    def autotune(self, steps=3):
+        bw, rows = ctypes.c_int32(), ctypes.c_int32()
+        ms = ctypes.c_double()
+        _bcheck(lib().lbpc_batch_autotune(self.h, int(steps),
+                                          ctypes.byref(bw), ctypes.byref(rows),
+                                          ctypes.byref(ms)), self.h)
+        return {"block_width": bw.value, "rows": rows.value,
+                "ms_per_step": ms.value}
+
+    def step(self, n=1):
+        _bcheck(lib().lbpc_batch_step(self.h, int(n)), self.h)
+
+    def rho_u_T(self, c):
+        cfg = self.cfgs[c]
+        out = [np.empty((cfg["ny"], cfg["nx"])) for _ in range(4)]
+        _bcheck(lib().lbpc_batch_get_rho_u_T(self.h, int(c), *map(_dp, out)),
+                self.h)
+        return tuple(out)
+
+    def diag(self, c) -> dict:
+        d = Diag()
+        _bcheck(lib().lbpc_batch_get_diag(self.h, int(c), ctypes.byref(d)),
+                self.h)
+        return {n: getattr(d, n) for n, _ in Diag._fields_ if n != "pad"}
+
+    def nodes(self) -> int:
+        v = ctypes.c_int64()
+        _bcheck(lib().lbpc_batch_nodes(self.h, ctypes.byref(v)), self.h)
+        return v.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbpc_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):
