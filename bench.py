@@ -65,6 +65,37 @@ def gpu_run(n, prec, steps, warmup, per_launch=40):
     return ms_total / steps, kern_ms, cfg
 
 
+def batch_run(count, steps, warmup):
+    """The batched sweep: `count` heated-wall droplets of sizes drawn from
+    {64, 96, ..., 512}, FP32 storage, one persistent launch per step,
+    graph-replayed steps, autotuned tiles."""
+    import torch
+    from paper_1709_04400_amd import inputs, lbpc
+    cases = inputs.batch_cases(count=count, seed=1709,
+                               precision=inputs.FP32)
+    b = lbpc.Batch([c for c, _ in cases])
+    for k, (_, f) in enumerate(cases):
+        b.init_fields(k, f["rho"], f["ux"], f["uy"], f["T"])
+    del cases
+    stream = b.stream
+    b.step(warmup)
+    tune = b.autotune(steps=3)   # steady-state timings, state unchanged
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    nodes = b.nodes()
+    bad = sum(b.diag(k)["nonfinite"] for k in range(0, count, 17))
+    b.close()
+    if bad:
+        raise RuntimeError("non-finite state in the batched run")
+    return ms, nodes, tune
+
+
 def cpu_baseline(n_sample=512, steps=150):
     """The FP64 oracle, single thread, on a crop of the same recipe."""
     import oracle
@@ -92,6 +123,8 @@ def main():
     ap.add_argument("--variants", type=int, default=1,
                     help="also time the reduced-precision storage forms")
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=256,
+                    help="lattices in the batched sweep (0: skip it)")
     ap.add_argument("--per-launch", type=int, default=40)
     ap.add_argument("--traffic-file", default=os.path.join(
         ROOT, "profiles", "traffic_k_step_fp64_spinodal4096.md"))
@@ -147,6 +180,17 @@ def main():
                 "frac": round(vb / HBM_PEAK_GBS, 4),
                 "bytes_per_lup": BYTES_PER_LUP[prec]}
         out["variants"] = var
+    if args.batch:
+        bsteps = max(args.steps // 10, 50)
+        bms, bnodes, tune = batch_run(args.batch, bsteps, args.warmup)
+        bb = BYTES_PER_LUP[1] * bnodes / (bms * 1e-3) / 1e9
+        out.setdefault("variants", {})["BATCHED_FP32"] = {
+            "MLUPS": round(bnodes / bms / 1e3, 1), "ms_per_step": round(bms, 5),
+            "dtype": "f32", "lattices": args.batch, "nodes": bnodes,
+            "steps": bsteps, "alg_GBs": round(bb, 1),
+            "frac": round(bb / HBM_PEAK_GBS, 4), "tiles": tune,
+            "workload": "heated-wall droplets, sizes U{64..512 step 32}, "
+                        "R = 0.2 N, T_w ~ U[1.02, 1.2] T_sat, seed 1709"}
     if args.cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -146,6 +146,18 @@ lbpc_status lbpc_init_fields(lbpc_handle *h, const double *rho,
  * waiting.  A non-finite state is reported by the next synchronising call. */
 lbpc_status lbpc_step(lbpc_handle *h, int64_t n);
 
+/* Tile shape of the step launches: threads per block (64, 128 or 256; the
+ * strip is that many columns minus 4 halo columns) and rows per tile (>= 4).
+ * Results do not depend on it. */
+lbpc_status lbpc_set_tiles(lbpc_handle *h, int32_t block_width, int32_t rows);
+
+/* Times `steps` launches of each candidate tile shape (block width 64, 128,
+ * 256 x rows 4 ... 64) on the current state, keeps the fastest and reports
+ * it.  State and phi history are left unchanged (timing launches write phi
+ * to scratch).  Blocks until done. */
+lbpc_status lbpc_autotune(lbpc_handle *h, int32_t steps, int32_t *block_width,
+                          int32_t *rows, double *ms_per_step);
+
 /* Waits for the stream; writes rho, v = (j + F/2)/rho and T at the current
  * time level into host FP64 arrays [ny][nx] (any pointer may be NULL).
  * Returns LBPC_ERR_NUMERIC if a non-finite value is present. */
@@ -195,9 +207,12 @@ lbpc_status lbpc_batch_init_fields(lbpc_batch *b, int32_t c,
 /* Tile shape: threads per block (64, 128 or 256) and rows per tile (>= 4). */
 lbpc_status lbpc_batch_set_tiles(lbpc_batch *b, int32_t block_width,
                                  int32_t rows);
-/* Times `steps` launches of each candidate tile shape on the initialised
- * state (which it leaves unchanged: allowed only before the first step),
- * keeps the fastest and reports it.  Blocks until done. */
+/* Times `steps` launches of each candidate tile shape (block width 64, 128,
+ * 256 x rows 16, 24, 32, 48, 64) on the current state, keeps the fastest and
+ * reports it.  The state and the phi history are left unchanged (timing
+ * launches write phi to scratch).  Before the first step the launches read
+ * the initial state in place, so tune after a step for steady-state
+ * timings.  Blocks until done. */
 lbpc_status lbpc_batch_autotune(lbpc_batch *b, int32_t steps,
                                 int32_t *block_width, int32_t *rows,
                                 double *ms_per_step);

@@ -10,6 +10,9 @@
 #include <string>
 #include <vector>
 
+#include <array>
+#include <vector>
+
 #include "lbpc_host.h"
 
 using namespace lbpc_host;
@@ -31,6 +34,12 @@ struct lbpc_handle {
   int initialised;
   int64_t step;
   double rho_ave;
+  // non-periodic lattices run the persistent tile kernel, which reads its
+  // parameters from a device table (one entry per buffer parity)
+  int tiled;
+  int table_fresh, table_phi_valid, table_valid, table_tuning;
+  int nwork, grid;
+  StepParams table_host[2];
   std::string err;
 };
 
@@ -65,10 +74,81 @@ StepParams params_now(lbpc_handle* h) {
   p.fout = at(h, h->L.dist[1 - h->cur][0]);
   p.gout = at(h, h->L.dist[1 - h->cur][1]);
   p.phi = at(h, h->L.phi);
+  p.phi_out = p.phi;
   p.fresh = h->fresh;
   p.phi_valid = h->phi_valid;
   p.rho_ave = h->rho_ave;
   return p;
+}
+
+// tile shape of the step launches; the tile list of the non-periodic path
+// is rebuilt (and re-uploaded) at the next launch
+void set_tiles_impl(lbpc_handle* h, int bw, int rows) {
+  StepParams& p = h->base;
+  p.bw = bw;
+  p.W = bw - 2 * lbpc::HALO;
+  p.nbx = (h->cfg.nx + p.W - 1) / p.W;
+  p.H = rows;
+  p.nby = (h->cfg.ny + p.H - 1) / p.H;
+  if (h->tiled) {
+    h->nwork = p.nbx * p.nby;
+    h->grid = tile_grid(h->nwork, h->cfg.precision, bw);
+    h->table_valid = 0;
+  }
+}
+
+// one launch of the step on the current state (buffer cur -> 1 - cur); the
+// caller flips the state afterwards, except for the autotuner, whose timing
+// launches send phi(t) to scratch and leave the state as it is
+lbpc_status enqueue_step(lbpc_handle* h, bool tuning) {
+  StepParams p = params_now(h);
+  if (tuning) p.phi_out = at(h, h->L.tune_phi);
+  if (!h->tiled)
+    return lbpc::launch_step(p, h->cfg.precision, h->stream) == hipSuccess
+               ? LBPC_OK
+               : fail(h, LBPC_ERR_HIP, "step kernel launch");
+  if (!h->table_valid) {
+    const StepParams& b = h->base;
+    std::vector<std::array<int, 4>> tiles;
+    for (int by = 0; by < b.nby; ++by)
+      for (int bx = 0; bx < b.nbx; ++bx) tiles.push_back({0, bx, by, 0});
+    std::vector<std::array<int, 4>> work = xcd_order(tiles);
+    HIP_TRY(h,
+            hipMemcpyAsync(at(h, h->L.work), work.data(),
+                           work.size() * sizeof(work[0]),
+                           hipMemcpyHostToDevice, h->stream),
+            "tile list upload");
+    HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+    h->table_valid = 1;
+    h->table_fresh = -1;
+  }
+  const int want_tune = tuning ? 1 : 0;
+  if (h->table_fresh != h->fresh || h->table_phi_valid != h->phi_valid ||
+      h->table_tuning != want_tune) {
+    const int keep = h->cur;
+    for (int par = 0; par < 2; ++par) {
+      h->cur = par;
+      h->table_host[par] = params_now(h);
+      if (tuning) h->table_host[par].phi_out = at(h, h->L.tune_phi);
+    }
+    h->cur = keep;
+    HIP_TRY(h,
+            hipMemcpyAsync(at(h, h->L.table), h->table_host,
+                           sizeof(h->table_host), hipMemcpyHostToDevice,
+                           h->stream),
+            "parameter table upload");
+    HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+    h->table_fresh = h->fresh;
+    h->table_phi_valid = h->phi_valid;
+    h->table_tuning = want_tune;
+  }
+  HIP_TRY(h,
+          lbpc::launch_step_batch(
+              static_cast<const StepParams*>(at(h, h->L.table)),
+              at(h, h->L.work), h->nwork, h->cur, h->grid, h->cfg.precision,
+              p.bw, h->stream),
+          "step kernel");
+  return LBPC_OK;
 }
 
 }  // namespace
@@ -108,26 +188,25 @@ lbpc_status lbpc_create(const lbpc_config* cfg, void* dev_workspace,
   StepParams& p = h->base;
   derive_params(*cfg, p);
   {
-    // strip width (threads per block) and rows per block; LBPC_TILE_BW and
-    // LBPC_TILE_H override the defaults
+    // default tile shape; LBPC_TILE_BW and LBPC_TILE_H override it, and
+    // lbpc_autotune / lbpc_set_tiles change it
     int bw = env_int("LBPC_TILE_BW", 256);
     if (bw != 64 && bw != 128 && bw != 256) bw = 256;
-    p.bw = bw;
-    p.W = bw - 2 * lbpc::HALO;
-    p.nbx = (cfg->nx + p.W - 1) / p.W;
-    int h_rows = env_int("LBPC_TILE_H", 0);
-    if (h_rows <= 0) {
+    int rows = env_int("LBPC_TILE_H", 0);
+    if (rows <= 0) {
       // enough blocks to give each of the 256 CUs several, and at least 16
       // rows per block so the 4-row warm-up stays small
-      long long want = (2048LL * 256 / bw) / p.nbx;
+      const int nbx = (cfg->nx + bw - 2 * lbpc::HALO - 1) /
+                      (bw - 2 * lbpc::HALO);
+      long long want = (2048LL * 256 / bw) / nbx;
       if (want < 1) want = 1;
-      h_rows = (int)((cfg->ny + want - 1) / want);
-      if (h_rows < 16) h_rows = 16;
-      if (h_rows > 256) h_rows = 256;
+      rows = (int)((cfg->ny + want - 1) / want);
+      if (rows < 16) rows = 16;
+      if (rows > 256) rows = 256;
     }
-    p.H = h_rows;
-    p.nby = (cfg->ny + p.H - 1) / p.H;
     p.xcd_order = env_int("LBPC_XCD_ORDER", 1);
+    h->tiled = !(p.perx && p.pery);
+    set_tiles_impl(h, bw, rows);
   }
   *out = h;
   return LBPC_OK;
@@ -158,6 +237,7 @@ lbpc_status lbpc_init_fields(lbpc_handle* h, const double* rho,
   h->phi_valid = 0;
   h->step = 0;
   h->initialised = 1;
+  h->table_fresh = -1;
   return LBPC_OK;
 }
 
@@ -166,14 +246,69 @@ lbpc_status lbpc_step(lbpc_handle* h, int64_t n) {
   if (n < 0) return fail(h, LBPC_ERR_ARG, "n < 0");
   if (!h->initialised) return fail(h, LBPC_ERR_STATE, "step before init");
   for (int64_t s = 0; s < n; ++s) {
-    StepParams p = params_now(h);
-    HIP_TRY(h, lbpc::launch_step(p, h->cfg.precision, h->stream),
-            "step kernel");
+    lbpc_status st = enqueue_step(h, false);
+    if (st != LBPC_OK) return st;
     h->cur = 1 - h->cur;
     h->fresh = 0;
     h->phi_valid = 1;
     h->step += 1;
   }
+  return LBPC_OK;
+}
+
+lbpc_status lbpc_set_tiles(lbpc_handle* h, int32_t block_width,
+                           int32_t rows) {
+  if (!h) return fail(nullptr, LBPC_ERR_ARG, "handle is NULL");
+  if (block_width != 64 && block_width != 128 && block_width != 256)
+    return fail(h, LBPC_ERR_ARG, "block width must be 64, 128 or 256");
+  if (rows < 4) return fail(h, LBPC_ERR_ARG, "rows must be >= 4");
+  set_tiles_impl(h, block_width, rows);
+  return LBPC_OK;
+}
+
+lbpc_status lbpc_autotune(lbpc_handle* h, int32_t steps, int32_t* block_width,
+                          int32_t* rows, double* ms_per_step) {
+  if (!h) return fail(nullptr, LBPC_ERR_ARG, "handle is NULL");
+  if (steps < 1) return fail(h, LBPC_ERR_ARG, "steps < 1");
+  if (!h->initialised) return fail(h, LBPC_ERR_STATE, "autotune before init");
+  static const int CBW[3] = {64, 128, 256};
+  static const int CH[7] = {4, 8, 16, 24, 32, 48, 64};
+  hipEvent_t e0, e1;
+  HIP_TRY(h, hipEventCreate(&e0), "event");
+  HIP_TRY(h, hipEventCreate(&e1), "event");
+  float best = 1e30f;
+  int best_bw = h->base.bw, best_rows = h->base.H;
+  lbpc_status st = LBPC_OK;
+  for (int bw : CBW) {
+    for (int r : CH) {
+      if (r > h->cfg.ny) continue;
+      set_tiles_impl(h, bw, r);
+      st = enqueue_step(h, true);  // warm-up (and uploads)
+      if (st != LBPC_OK) break;
+      hipError_t e = hipEventRecord(e0, h->stream);
+      for (int k = 0; k < steps && st == LBPC_OK; ++k)
+        st = enqueue_step(h, true);
+      if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess && st == LBPC_OK) st = hip_fail(h, e, "timing");
+      if (st != LBPC_OK) break;
+      if (ms < best) {
+        best = ms;
+        best_bw = bw;
+        best_rows = r;
+      }
+    }
+    if (st != LBPC_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  set_tiles_impl(h, best_bw, best_rows);
+  if (st != LBPC_OK) return st;
+  if (block_width) *block_width = best_bw;
+  if (rows) *rows = best_rows;
+  if (ms_per_step) *ms_per_step = best / steps;
   return LBPC_OK;
 }
 
@@ -310,6 +445,7 @@ lbpc_status lbpc_load_state(lbpc_handle* h, const void* host, size_t bytes) {
   h->step = meta[2];
   h->fresh = 1;
   h->initialised = 1;
+  h->table_fresh = -1;
   return LBPC_OK;
 }
 

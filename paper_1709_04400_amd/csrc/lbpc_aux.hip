@@ -64,10 +64,10 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_macro1(StepParams p,
   const long long i = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
   if (i >= N) return;
   const int x = (int)(i % p.nx), y = (int)(i / p.nx);
-  C fsh[Q], gsh[Q], fn[Q], gn[Q];
-  storage_shifts<P>(p, fsh, gsh);
+  C fn[Q], gn[Q];
+  const Shift<P> sh(p);
   pull_node<P, GEN>(p, static_cast<const typename Tr::S*>(p.fin),
-                    static_cast<const typename Tr::S*>(p.gin), x, y, fsh, gsh,
+                    static_cast<const typename Tr::S*>(p.gin), x, y, sh,
                     fn, gn);
   C m[Q];
   to_moments(fn, m);
@@ -171,10 +171,10 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_canon(StepParams p, int which,
   const long long i = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
   if (i >= N) return;
   const int x = (int)(i % p.nx), y = (int)(i / p.nx);
-  C fsh[Q], gsh[Q], fn[Q], gn[Q];
-  storage_shifts<P>(p, fsh, gsh);
+  C fn[Q], gn[Q];
+  const Shift<P> sh(p);
   pull_node<P, GEN>(p, static_cast<const typename Tr::S*>(p.fin),
-                    static_cast<const typename Tr::S*>(p.gin), x, y, fsh, gsh,
+                    static_cast<const typename Tr::S*>(p.gin), x, y, sh,
                     fn, gn);
   C v = C(0);
 #pragma unroll

@@ -28,6 +28,7 @@ constexpr int MIN_ROWS = 4;
 struct CaseLayout {
   size_t dist[2][2];
   size_t phi;
+  size_t tune_phi;  // phi(t) written here while the autotuner times steps
 };
 
 struct BatchLayout {
@@ -75,6 +76,8 @@ BatchLayout plan_batch(const lbpc_config* cfgs, int n) {
       }
     L.cases[c].phi = off;
     off += align_up(N * compute_bytes(cfgs[c].precision));
+    L.cases[c].tune_phi = off;
+    off += align_up(N * compute_bytes(cfgs[c].precision));
   }
   L.total = off;
   return L;
@@ -110,6 +113,7 @@ struct lbpc_batch {
   int64_t step;
   int bw, rows, nwork, grid;
   int table_fresh, table_phi_valid;  // flags the uploaded table carries
+  int tuning;  // timing launches: state read in place, phi(t) to scratch
   hipGraphExec_t graph[2];
   int use_graph;
   std::string err;
@@ -144,6 +148,7 @@ StepParams case_params(lbpc_batch* b, int c, int par) {
   p.fout = at(b, cl.dist[1 - par][0]);
   p.gout = at(b, cl.dist[1 - par][1]);
   p.phi = at(b, cl.phi);
+  p.phi_out = b->tuning ? at(b, cl.tune_phi) : p.phi;
   p.fresh = b->fresh;
   p.phi_valid = b->phi_valid;
   p.rho_ave = b->rho_ave[c];
@@ -189,30 +194,23 @@ lbpc_status build_work(lbpc_batch* b) {
     return (long long)b->cfgs[x].nx * b->cfgs[x].ny >
            (long long)b->cfgs[y].nx * b->cfgs[y].ny;
   });
-  b->work_host.clear();
+  std::vector<WorkItem> tiles;
   for (int c : order) {
     const int nbx = (b->cfgs[c].nx + W - 1) / W;
     const int nby = (b->cfgs[c].ny + b->rows - 1) / b->rows;
     for (int by = 0; by < nby; ++by)
-      for (int bx = 0; bx < nbx; ++bx) b->work_host.push_back({c, bx, by, 0});
+      for (int bx = 0; bx < nbx; ++bx) tiles.push_back({c, bx, by, 0});
   }
-  if (b->work_host.size() > b->L.work_capacity)
+  if (tiles.size() > b->L.work_capacity)
     return bfail(b, LBPC_ERR_OOM, "work list exceeds its reserved space");
+  b->work_host = xcd_order(tiles);
   b->nwork = (int)b->work_host.size();
   BHIP(b,
        hipMemcpyAsync(at(b, b->L.work), b->work_host.data(),
                       b->work_host.size() * sizeof(WorkItem),
                       hipMemcpyHostToDevice, b->stream),
        "work list upload");
-  // one persistent block per resident slot: CUs x blocks per CU (registers
-  // allow 2 waves per SIMD in FP64, 3 otherwise; 4 SIMDs per CU)
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess)
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
-                                dev);
-  const int waves = b->prec == LBPC_FP64 ? 2 : 3;
-  const int per_cu = std::max(1, 4 * waves / (b->bw / 64));
-  b->grid = std::max(1, std::min(b->nwork, cus * per_cu));
+  b->grid = tile_grid(b->nwork, b->prec, b->bw);
   drop_graphs(b);
   return upload_table(b);
 }
@@ -332,44 +330,49 @@ lbpc_status lbpc_batch_autotune(lbpc_batch* b, int32_t steps,
   for (int c = 0; c < b->n; ++c)
     if (!b->initialised[c])
       return bfail(b, LBPC_ERR_STATE, "autotune before every lattice is set");
-  // the initialised state is read in place (fresh) and phi_prev is unused
-  // until the first real step, so timing launches leave the state unchanged
-  if (b->step != 0 || !b->fresh || b->phi_valid)
-    return bfail(b, LBPC_ERR_STATE, "autotune only before the first step");
+  // timing launches read the current buffer and write the other one (whose
+  // contents the next real step overwrites) and send phi(t) to scratch, so
+  // the state and the phi history are left as they are
   hipEvent_t e0, e1;
   BHIP(b, hipEventCreate(&e0), "event");
   BHIP(b, hipEventCreate(&e1), "event");
   float best = 1e30f;
   int best_bw = b->bw, best_rows = b->rows;
-  for (int bw : CAND_BW)
+  b->tuning = 1;
+  lbpc_status st = LBPC_OK;
+  for (int bw : CAND_BW) {
     for (int h : CAND_H) {
       b->bw = bw;
       b->rows = h;
-      lbpc_status st = build_work(b);
-      if (st != LBPC_OK) return st;
-      st = launch(b, b->cur);  // warm-up
-      if (st != LBPC_OK) return st;
-      BHIP(b, hipEventRecord(e0, b->stream), "event");
-      for (int s = 0; s < steps; ++s) {
-        st = launch(b, b->cur);
-        if (st != LBPC_OK) return st;
-      }
-      BHIP(b, hipEventRecord(e1, b->stream), "event");
-      BHIP(b, hipEventSynchronize(e1), "event");
+      st = build_work(b);
+      if (st == LBPC_OK) st = launch(b, b->cur);  // warm-up
+      if (st != LBPC_OK) break;
+      hipError_t e = hipEventRecord(e0, b->stream);
+      for (int s = 0; s < steps && st == LBPC_OK; ++s) st = launch(b, b->cur);
+      if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;
-      BHIP(b, hipEventElapsedTime(&ms, e0, e1), "event");
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess && st == LBPC_OK)
+        st = bfail(b, LBPC_ERR_HIP, std::string("autotune timing: ") +
+                                        hipGetErrorString(e));
+      if (st != LBPC_OK) break;
       if (ms < best) {
         best = ms;
         best_bw = bw;
         best_rows = h;
       }
     }
+    if (st != LBPC_OK) break;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  b->tuning = 0;
   b->bw = best_bw;
   b->rows = best_rows;
-  lbpc_status st = build_work(b);
+  lbpc_status st2 = build_work(b);
   if (st != LBPC_OK) return st;
+  if (st2 != LBPC_OK) return st2;
   if (block_width) *block_width = best_bw;
   if (rows) *rows = best_rows;
   if (ms_per_step) *ms_per_step = best / steps;

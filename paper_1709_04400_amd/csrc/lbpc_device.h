@@ -50,7 +50,8 @@ struct StepParams {
   const void* gin;
   void* fout;       // [9][N] output f*(t)
   void* gout;
-  void* phi;        // [N] phi(t-1) in, phi(t) out (compute precision)
+  void* phi;        // [N] phi(t-1) in (compute precision)
+  void* phi_out;    // [N] phi(t) out; the same array except while tuning
   long long N;      // nx * ny
 };
 
@@ -173,6 +174,34 @@ __device__ __forceinline__ Ghost resolve(const StepParams& p, int x, int y) {
   return g;
 }
 
+// Shifts of the shifted storage forms: f is stored as f_a - w_a rho_ref and
+// g as g_a - wg_a T_ref.  Only three f shifts (rest, axis, diagonal) and two
+// g shifts (rest, moving) are distinct; zero for the plain forms.
+template <int P>
+struct Shift {
+  using C = typename Prec<P>::C;
+  C f0, f1, f2, g0, g1;
+  __device__ __forceinline__ explicit Shift(const StepParams& p) {
+    if constexpr (Prec<P>::shift) {
+      f0 = C(w_lat(0) * p.rho_ref);
+      f1 = C(w_lat(1) * p.rho_ref);
+      f2 = C(w_lat(5) * p.rho_ref);
+      g0 = C(w_rest(0) * p.T_ref);
+      g1 = C(w_rest(1) * p.T_ref);
+    } else {
+      f0 = f1 = f2 = g0 = g1 = C(0);
+    }
+  }
+  __device__ __forceinline__ C f(int a) const {
+    if constexpr (!Prec<P>::shift) return C(0);
+    return a == 0 ? f0 : (a < 5 ? f1 : f2);
+  }
+  __device__ __forceinline__ C g(int a) const {
+    if constexpr (!Prec<P>::shift) return C(0);
+    return a == 0 ? g0 : g1;
+  }
+};
+
 // ------------------------------------------------------------- the pull
 // f_a(x, t) = f*_a(x - e_a, t - 1), and likewise g, at lattice node (x, y),
 // with the side rules at edge nodes: across a wall halfway bounce-back for f
@@ -184,7 +213,7 @@ template <int P, bool GEN>
 __device__ __forceinline__ void pull_node(
     const StepParams& p, const typename Prec<P>::S* __restrict__ fin,
     const typename Prec<P>::S* __restrict__ gin, int x, int y,
-    const typename Prec<P>::C fsh[Q], const typename Prec<P>::C gsh[Q],
+    const Shift<P>& sh,
     typename Prec<P>::C fn[Q], typename Prec<P>::C gn[Q]) {
   using Tr = Prec<P>;
   using C = typename Tr::C;
@@ -194,8 +223,8 @@ __device__ __forceinline__ void pull_node(
   if (p.fresh) {
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-      fn[a] = Tr::ld(fin, a * N + row + x) + fsh[a];
-      gn[a] = Tr::ld(gin, a * N + row + x) + gsh[a];
+      fn[a] = Tr::ld(fin, a * N + row + x) + sh.f(a);
+      gn[a] = Tr::ld(gin, a * N + row + x) + sh.g(a);
     }
     return;
   }
@@ -213,8 +242,8 @@ __device__ __forceinline__ void pull_node(
                               rm + xm, rm + xp,  rp + xp, rp + xm};
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-      fn[a] = Tr::ld(fin, a * N + src[a]) + fsh[a];
-      gn[a] = Tr::ld(gin, a * N + src[a]) + gsh[a];
+      fn[a] = Tr::ld(fin, a * N + src[a]) + sh.f(a);
+      gn[a] = Tr::ld(gin, a * N + src[a]) + sh.g(a);
     }
     return;
   }
@@ -227,30 +256,18 @@ __device__ __forceinline__ void pull_node(
     Ghost gh = resolve(p, x - EXs[a], y - EYs[a]);
     if (gh.kind == GH_INSIDE) {
       const long long s = (long long)gh.y * nx + gh.x;
-      fn[a] = Tr::ld(fin, a * N + s) + fsh[a];
-      gn[a] = Tr::ld(gin, a * N + s) + gsh[a];
+      fn[a] = Tr::ld(fin, a * N + s) + sh.f(a);
+      gn[a] = Tr::ld(gin, a * N + s) + sh.g(a);
     } else if (gh.kind == GH_WALL) {
       const int o = OPs[a];
-      fn[a] = Tr::ld(fin, o * N + self) + fsh[o];
-      gn[a] = -(Tr::ld(gin, o * N + self) + gsh[o]) +
+      fn[a] = Tr::ld(fin, o * N + self) + sh.f(o);
+      gn[a] = -(Tr::ld(gin, o * N + self) + sh.g(o)) +
               C(2.0 * w_rest(a) * gh.T);
     } else {
       const long long s = (long long)gh.y * nx + gh.x;
-      fn[a] = Tr::ld(fin, a * N + s) + fsh[a];
+      fn[a] = Tr::ld(fin, a * N + s) + sh.f(a);
       gn[a] = C(w_rest(a) * gh.T);
     }
-  }
-}
-
-template <int P>
-__device__ __forceinline__ void storage_shifts(const StepParams& p,
-                                               typename Prec<P>::C fsh[Q],
-                                               typename Prec<P>::C gsh[Q]) {
-  using C = typename Prec<P>::C;
-#pragma unroll
-  for (int a = 0; a < Q; ++a) {
-    fsh[a] = Prec<P>::shift ? C(w_lat(a) * p.rho_ref) : C(0);
-    gsh[a] = Prec<P>::shift ? C(w_rest(a) * p.T_ref) : C(0);
   }
 }
 

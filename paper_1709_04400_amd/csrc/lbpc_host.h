@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/lbpc.h"
 #include "lbpc_device.h"
@@ -51,6 +52,9 @@ inline size_t compute_bytes(int prec) { return prec == LBPC_FP64 ? 8 : 4; }
 struct Layout {
   size_t dist[2][2];  // offsets of f / g of buffer 0 / 1
   size_t phi, scratch, partial, diag_out;
+  size_t table, work;  // parameter table and tile list (non-periodic path)
+  size_t work_capacity;
+  size_t tune_phi;     // phi(t) of the autotuner's timing launches
   size_t total;
 };
 
@@ -72,6 +76,14 @@ inline Layout plan(const lbpc_config& c) {
   off += align_up((size_t)lbpc::diag_blocks((long long)N) * 8 * sizeof(double));
   L.diag_out = off;
   off += align_up(8 * sizeof(double));
+  L.table = off;
+  off += align_up(2 * sizeof(StepParams));
+  // tiles of the narrowest strips (60 columns) and shortest runs (4 rows)
+  L.work_capacity = (size_t)((c.nx + 59) / 60) * (size_t)((c.ny + 3) / 4);
+  L.work = off;
+  off += align_up(L.work_capacity * 16);
+  L.tune_phi = off;
+  off += align_up(N * compute_bytes(c.precision));
   L.total = off;
   return L;
 }
@@ -182,6 +194,39 @@ inline const char* check_fields(const lbpc_config& c, const double* rho,
   }
   *rho_ave = sum / (double)N;
   return nullptr;
+}
+
+// Order tiles for the XCDs: workgroup w runs on XCD w % 8, so item w gets
+// tile t of a contiguous 1/8 of the list, and the tiles one XCD works on at
+// the same time are neighbours that share halo rows and columns in its L2.
+template <class T>
+inline std::vector<T> xcd_order(const std::vector<T>& tiles) {
+  const int nb = (int)tiles.size();
+  std::vector<T> out(tiles.size());
+  const int per = (nb + 7) / 8;
+  const int full = nb - 8 * (per - 1);
+  for (int w = 0; w < nb; ++w) {
+    const int xcd = w % 8, k = w / 8;
+    const int t = xcd < full ? xcd * per + k
+                             : full * per + (xcd - full) * (per - 1) + k;
+    out[w] = tiles[t];
+  }
+  return out;
+}
+
+// Blocks of the tile kernel: one per tile (the hardware schedules them), or,
+// with LBPC_PERSISTENT=1, one per resident slot walking the list.
+inline int tile_grid(int nwork, int prec, int bw) {
+  const char* v = std::getenv("LBPC_PERSISTENT");
+  if (!(v && std::atoi(v) != 0)) return nwork;
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                dev);
+  const int waves = prec == LBPC_FP64 ? 2 : 3;
+  int per_cu = 4 * waves / (bw / 64);
+  if (per_cu < 1) per_cu = 1;
+  return nwork < cus * per_cu ? nwork : cus * per_cu;
 }
 
 inline int env_int(const char* name, int dflt) {

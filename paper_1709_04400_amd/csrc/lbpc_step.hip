@@ -78,7 +78,8 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
   const S* __restrict__ gin = static_cast<const S*>(p.gin);
   S* __restrict__ fout = static_cast<S*>(p.fout);
   S* __restrict__ gout = static_cast<S*>(p.gout);
-  C* __restrict__ phiv = static_cast<C*>(p.phi);
+  const C* __restrict__ phiv = static_cast<const C*>(p.phi);
+  C* __restrict__ phio = static_cast<C*>(p.phi_out);
 
   // column roles
   bool ghostc = false;
@@ -100,8 +101,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
     if (c + 1 >= nx) ttp = t;
   }
 
-  C fsh[Q], gsh[Q];
-  storage_shifts<P>(p, fsh, gsh);
+  const Shift<P> sh(p);
   C sf[Q], sg[Q];
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
@@ -133,7 +133,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
   {
     const int rw = wrap_row(rfirst);
     if (doA && rw >= 0)
-      pull_node<P, GEN>(p, fin, gin, cw, rw, fsh, gsh, fc, gc);
+      pull_node<P, GEN>(p, fin, gin, cw, rw, sh, fc, gc);
   }
 
   for (int it = 0; it < nit; ++it) {
@@ -265,7 +265,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
           from_moments(ms, fo);
           const long long o = (long long)rb * nx + c;
 #pragma unroll
-          for (int a = 0; a < Q; ++a) Tr::st(fout, a * N + o, fo[a] - fsh[a]);
+          for (int a = 0; a < Q; ++a) Tr::st(fout, a * N + o, fo[a] - sh.f(a));
         }
       }
     }
@@ -278,7 +278,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
     {
       const int rwn = (it + 1 < nit) ? wrap_row(r + dir) : -1;
       if (doA && rwn >= 0)
-        pull_node<P, GEN>(p, fin, gin, cw, rwn, fsh, gsh, fc, gn);
+        pull_node<P, GEN>(p, fin, gin, cw, rwn, sh, fc, gn);
     }
     __syncthreads();
 
@@ -363,7 +363,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
           const C prev = p.phi_valid ? phiv[o] : phi;
           S0 = phi + C(0.5) * (phi - prev);
         }
-        phiv[o] = phi;
+        phio[o] = phi;
         // improved thermal MRT collision: Eqs. (45), (46), (53)-(55)
         C n[Q], ns[Q], go[Q];
         to_moments(gq2, n);
@@ -383,7 +383,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
         }
         from_moments(ns, go);
 #pragma unroll
-        for (int a = 0; a < Q; ++a) Tr::st(gout, a * N + o, go[a] - gsh[a]);
+        for (int a = 0; a < Q; ++a) Tr::st(gout, a * N + o, go[a] - sh.g(a));
       }
     }
 
@@ -438,11 +438,10 @@ k_step_batch(const StepParams* __restrict__ table,
 hipError_t launch_step(const StepParams& p, int prec, hipStream_t s) {
   const dim3 grid(p.nbx * p.nby);
   const bool gen = !(p.perx && p.pery);
+  // lattices with a non-periodic side run the persistent tile kernel
+  if (gen) return hipErrorInvalidValue;
 #define LBPC_LAUNCH_BW(PR, BW)                                              \
-  if (gen)                                                                  \
-    hipLaunchKernelGGL((k_step<PR, true, BW>), grid, dim3(BW), 0, s, p);    \
-  else                                                                      \
-    hipLaunchKernelGGL((k_step<PR, false, BW>), grid, dim3(BW), 0, s, p);
+  hipLaunchKernelGGL((k_step<PR, false, BW>), grid, dim3(BW), 0, s, p);
 #define LBPC_LAUNCH(PR)                                                     \
   if (p.bw == 64) {                                                         \
     LBPC_LAUNCH_BW(PR, 64)                                                  \

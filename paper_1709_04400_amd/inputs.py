@@ -155,12 +155,21 @@ def batch_sizes(count=256, seed=1709):
     return [int(s) for s in sizes], [float(t) for t in tb]
 
 
+def heated_droplet(n, radius, T_w_over_Ts, precision=FP64):
+    """Droplet at T_sat in vapour at T_sat inside a closed n x n box whose
+    no-slip walls are held at T_w; constant lambda; no gravity."""
+    Tw = T_w_over_Ts * T_SAT
+    cfg = base_config(n, n, bc=[BC_WALL] * 4, T_bc=[Tw] * 4,
+                      precision=precision)
+    return cfg, droplet_fields(n, n, radius)
+
+
 def batch_cases(count=256, seed=1709, precision=FP32):
-    """The batched evaporation sweep: one evaporation case per draw, droplet
-    radius 0.2 x grid size."""
-    sizes, tb = batch_sizes(count, seed)
-    return [evaporation(n, 0.2 * n, t, precision=precision)
-            for n, t in zip(sizes, tb)]
+    """The batched evaporation sweep: one heated-wall droplet per draw,
+    droplet radius 0.2 x grid size."""
+    sizes, tw = batch_sizes(count, seed)
+    return [heated_droplet(n, 0.2 * n, t, precision=precision)
+            for n, t in zip(sizes, tw)]
 
 
 def random_rates(seed, lo=0.6, hi=1.6):

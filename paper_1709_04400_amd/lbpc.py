@@ -24,7 +24,7 @@ EXPORTS = (
     "lbpc_workspace_bytes", "lbpc_create", "lbpc_init_fields", "lbpc_step",
     "lbpc_get_rho_u_T", "lbpc_get_diag", "lbpc_state_bytes",
     "lbpc_save_state", "lbpc_load_state", "lbpc_destroy", "lbpc_last_error",
-    "lbpc_batch_workspace_bytes", "lbpc_batch_create",
+    "lbpc_set_tiles", "lbpc_autotune", "lbpc_batch_workspace_bytes", "lbpc_batch_create",
     "lbpc_batch_init_fields", "lbpc_batch_set_tiles", "lbpc_batch_autotune",
     "lbpc_batch_step", "lbpc_batch_get_rho_u_T", "lbpc_batch_get_diag",
     "lbpc_batch_nodes", "lbpc_batch_destroy", "lbpc_batch_last_error",
@@ -100,6 +100,9 @@ def lib():
         L.lbpc_last_error.argtypes = [vp]
         L.lbpc_last_error.restype = ctypes.c_char_p
         i32, i64p = ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)
+        L.lbpc_set_tiles.argtypes = [vp, i32, i32]
+        L.lbpc_autotune.argtypes = [vp, i32, ctypes.POINTER(i32),
+                                    ctypes.POINTER(i32), dp]
         L.lbpc_batch_workspace_bytes.argtypes = [
             ctypes.POINTER(Config), i32, ctypes.POINTER(ctypes.c_size_t)]
         L.lbpc_batch_create.argtypes = [ctypes.POINTER(Config), i32, vp,
@@ -238,6 +241,19 @@ class Simulation:
 
     def rho_u_T(self):
         return lbpc_get_rho_u_T(self.h, (self.ny, self.nx))
+
+    def set_tiles(self, block_width, rows):
+        _check(lib().lbpc_set_tiles(self.h, int(block_width), int(rows)),
+               self.h)
+
+    def autotune(self, steps=3):
+        bw, rows = ctypes.c_int32(), ctypes.c_int32()
+        ms = ctypes.c_double()
+        _check(lib().lbpc_autotune(self.h, int(steps), ctypes.byref(bw),
+                                   ctypes.byref(rows), ctypes.byref(ms)),
+               self.h)
+        return {"block_width": bw.value, "rows": rows.value,
+                "ms_per_step": ms.value}
 
     def diag(self) -> dict:
         return lbpc_get_diag(self.h)

@@ -96,19 +96,23 @@ def test_graph_replay_equals_eager(monkeypatch):
 
 
 def test_autotune_picks_a_shape_and_leaves_the_state():
+    """Tuning before the first step and again mid-run (steady state) changes
+    nothing in the results."""
     cases = I.batch_cases(count=6, seed=8, precision=I.FP32)
     tuned = _batch(cases)
     res = tuned.autotune(steps=2)
     assert res["block_width"] in (64, 128, 256) and res["rows"] >= 4
     assert res["ms_per_step"] > 0
     plain = _batch(cases)
-    tuned.step(30)
-    plain.step(30)
+    tuned.step(17)
+    plain.step(17)
+    res2 = tuned.autotune(steps=2)
+    assert res2["ms_per_step"] > 0
+    tuned.step(13)
+    plain.step(13)
     for k in range(len(cases)):
         for x, y in zip(tuned.rho_u_T(k), plain.rho_u_T(k)):
             assert np.array_equal(x, y), k
-    with pytest.raises(_lb().LbpcError):
-        tuned.autotune(steps=1)   # only before the first step
     tuned.close()
     plain.close()
 

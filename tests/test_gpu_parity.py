@@ -156,3 +156,27 @@ def test_diag_matches_oracle():
         assert np.isclose(dg[k], do[k], rtol=1e-11, atol=1e-14), k
     assert dg["radius_count"] == do["radius_count"]
     assert dg["step"] == 100 and not dg["nonfinite"]
+
+
+@pytest.mark.parametrize("which", ["periodic", "walls"])
+def test_autotune_and_tiles_leave_results_unchanged(which):
+    """Tile shape is a schedule, not arithmetic: any shape and a mid-run
+    autotune give bitwise the same fields."""
+    cfg, fl = I.static_droplet(100, 100, 25.0)
+    if which == "walls":
+        cfg.update(bc=[I.BC_WALL] * 4, T_bc=[1.1 * I.T_SAT] * 4)
+    ref = _gpu().Simulation(cfg)
+    ref.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
+    ref.step(40)
+    out = ref.rho_u_T()
+    ref.close()
+    g = _gpu().Simulation(cfg)
+    g.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
+    g.set_tiles(64, 7)
+    g.step(15)
+    res = g.autotune(steps=2)
+    assert res["block_width"] in (64, 128, 256) and res["rows"] >= 4
+    g.step(25)
+    for a, b in zip(g.rho_u_T(), out):
+        assert np.array_equal(a, b)
+    g.close()
