@@ -146,7 +146,8 @@ lbpc_status enqueue_step(lbpc_handle* h, bool tuning) {
           lbpc::launch_step_batch(
               static_cast<const StepParams*>(at(h, h->L.table)),
               at(h, h->L.work), h->nwork, h->cur, h->grid, h->cfg.precision,
-              p.bw, h->stream),
+              p.bw, h->stream,
+              !(p.perx && p.pery) || env_int("LBPC_FORCE_GEN", 0)),
           "step kernel");
   return LBPC_OK;
 }
@@ -205,7 +206,7 @@ lbpc_status lbpc_create(const lbpc_config* cfg, void* dev_workspace,
       if (rows > 256) rows = 256;
     }
     p.xcd_order = env_int("LBPC_XCD_ORDER", 1);
-    h->tiled = !(p.perx && p.pery);
+    h->tiled = !(p.perx && p.pery) || env_int("LBPC_FORCE_TILED", 0);
     set_tiles_impl(h, bw, rows);
   }
   *out = h;

@@ -57,34 +57,70 @@ struct StepParams {
 
 // ------------------------------------------------------- precision traits
 
+// Accesses to the distribution buffers go through global (address space 1)
+// pointers: they are device memory, and a pointer read from a parameter
+// table would otherwise be accessed with flat instructions.
+template <class T> using Gbl = __attribute__((address_space(1))) T;
+template <class T>
+__device__ __forceinline__ const Gbl<T>* gbl(const T* p) {
+  return (const Gbl<T>*)p;
+}
+template <class T>
+__device__ __forceinline__ Gbl<T>* gbl(T* p) { return (Gbl<T>*)p; }
+
+// S: storage type; C: compute type; R: register image of a loaded value.
+// A pulled value is kept as R until it is used, so a load can stay in
+// flight across the work between its issue and its use; cvt() turns it into
+// a compute value.
 template <int P> struct Prec;
 template <> struct Prec<0> {  // FP64 storage and arithmetic
   using S = double;
   using C = double;
+  using R = double;
   static constexpr bool shift = false;
-  __device__ static C ld(const S* p, long long i) { return p[i]; }
-  __device__ static void st(S* p, long long i, C v) { p[i] = v; }
+  __device__ static R ldr(const S* p, long long i) { return gbl(p)[i]; }
+  __device__ static C cvt(R v) { return v; }
+  __device__ static C ld(const S* p, long long i) { return gbl(p)[i]; }
+  __device__ static void st(S* p, long long i, C v) { gbl(p)[i] = v; }
 };
 template <> struct Prec<1> {  // FP32 storage and arithmetic
   using S = float;
   using C = float;
+  using R = float;
   static constexpr bool shift = false;
-  __device__ static C ld(const S* p, long long i) { return p[i]; }
-  __device__ static void st(S* p, long long i, C v) { p[i] = v; }
+  __device__ static R ldr(const S* p, long long i) { return gbl(p)[i]; }
+  __device__ static C cvt(R v) { return v; }
+  __device__ static C ld(const S* p, long long i) { return gbl(p)[i]; }
+  __device__ static void st(S* p, long long i, C v) { gbl(p)[i] = v; }
 };
 template <> struct Prec<2> {  // FP32 deviations from the rest equilibrium
   using S = float;
   using C = float;
+  using R = float;
   static constexpr bool shift = true;
-  __device__ static C ld(const S* p, long long i) { return p[i]; }
-  __device__ static void st(S* p, long long i, C v) { p[i] = v; }
+  __device__ static R ldr(const S* p, long long i) { return gbl(p)[i]; }
+  __device__ static C cvt(R v) { return v; }
+  __device__ static C ld(const S* p, long long i) { return gbl(p)[i]; }
+  __device__ static void st(S* p, long long i, C v) { gbl(p)[i] = v; }
 };
 template <> struct Prec<3> {  // FP16 deviations, FP32 arithmetic
   using S = __half;
   using C = float;
+  // the binary16 bits, one value per 32-bit register (packing two would
+  // need the loads to have landed)
+  using R = unsigned int;
   static constexpr bool shift = true;
-  __device__ static C ld(const S* p, long long i) { return __half2float(p[i]); }
-  __device__ static void st(S* p, long long i, C v) { p[i] = __float2half_rn(v); }
+  __device__ static R ldr(const S* p, long long i) {
+    return gbl(reinterpret_cast<const unsigned short*>(p))[i];
+  }
+  __device__ static C cvt(R v) {
+    return __half2float(__ushort_as_half((unsigned short)v));
+  }
+  __device__ static C ld(const S* p, long long i) { return cvt(ldr(p, i)); }
+  __device__ static void st(S* p, long long i, C v) {
+    gbl(reinterpret_cast<unsigned short*>(p))[i] =
+        __half_as_ushort(__float2half_rn(v));
+  }
 };
 
 // D2Q9 weights (shift of f) and rest weights of Eq. (53) (shift of g)
@@ -206,69 +242,156 @@ struct Shift {
 // f_a(x, t) = f*_a(x - e_a, t - 1), and likewise g, at lattice node (x, y),
 // with the side rules at edge nodes: across a wall halfway bounce-back for f
 // and anti-bounce-back g_a = -g*_abar + 2 wg_a T_wall for g; across an open
-// side f_a = f*_a(clamped source), g_a = wg_a T_side.  With p.fresh the
-// buffers hold f(t), g(t) themselves and are read in place.  Values are
-// returned unshifted, in compute precision.
+// side f_a = f*_a(clamped source), g_a = wg_a T_side.  A wall wins over an
+// open side at a corner and the y side gives the temperature there.  With
+// p.fresh the buffers hold f(t), g(t) themselves and are read in place.
+//
+// The pull is split in two so that its loads can be issued a row ahead:
+//   pull_raw  issues the loads.  Source rows / columns are clamped on
+//             non-periodic axes, and a wave holding an edge node takes, for
+//             each wall-crossing direction, f*_abar and g*_abar of the node
+//             itself (branch-free inside the wave).
+//   cook_f,   turn the raw registers into unshifted compute values; cook_g
+//   cook_g    then applies the value rules of g at edge nodes (again only
+//             in waves that hold one).
+
+constexpr int EXs[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int EYs[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int OPs[Q] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+// Which sides the pull of node (x, y) crosses.
+struct EdgeSides {
+  bool o0, o1, o2, o3;  // x-, x+, y-, y+
+  __device__ __forceinline__ EdgeSides(const StepParams& p, int x, int y,
+                                       bool gen) {
+    const bool clx = gen && !p.perx, cly = gen && !p.pery;
+    o0 = clx && x == 0;
+    o1 = clx && x == p.nx - 1;
+    o2 = cly && y == 0;
+    o3 = cly && y == p.ny - 1;
+  }
+  __device__ __forceinline__ bool any() const { return o0 || o1 || o2 || o3; }
+  // direction a crosses a side / a wall
+  __device__ __forceinline__ bool ox(int a) const {
+    return EXs[a] > 0 ? o0 : (EXs[a] < 0 ? o1 : false);
+  }
+  __device__ __forceinline__ bool oy(int a) const {
+    return EYs[a] > 0 ? o2 : (EYs[a] < 0 ? o3 : false);
+  }
+  __device__ __forceinline__ bool wall(const StepParams& p, int a) const {
+    return (ox(a) && p.bc[EXs[a] > 0 ? 0 : 1] == BC_WALL) ||
+           (oy(a) && p.bc[EYs[a] > 0 ? 2 : 3] == BC_WALL);
+  }
+};
+
+// Neighbour column x + dx: wrapped on a periodic x axis, clamped otherwise.
+__device__ __forceinline__ int wrap_or_clamp(int v, int n, bool periodic) {
+  if (v < 0) return periodic ? v + n : 0;
+  if (v >= n) return periodic ? v - n : n - 1;
+  return v;
+}
+
+template <int P, bool GEN>
+__device__ __forceinline__ void pull_raw(
+    const StepParams& p, const typename Prec<P>::S* __restrict__ fin,
+    const typename Prec<P>::S* __restrict__ gin, int x, int y,
+    typename Prec<P>::R fr[Q], typename Prec<P>::R gr[Q]) {
+  using Tr = Prec<P>;
+  const int nx = p.nx, ny = p.ny;
+  const long long N = p.N;
+  const long long self = (long long)y * nx + x;
+  // element offset of each direction's source; one set of loads serves
+  // every case below, so the loads never sit in divergent branches
+  long long off[Q];
+  if (p.fresh) {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) off[a] = a * N + self;
+  } else {
+    const int xm = wrap_or_clamp(x - 1, nx, !GEN || p.perx);
+    const int xp = wrap_or_clamp(x + 1, nx, !GEN || p.perx);
+    const int ym = wrap_or_clamp(y - 1, ny, !GEN || p.pery);
+    const int yp = wrap_or_clamp(y + 1, ny, !GEN || p.pery);
+    const long long row = (long long)y * nx;
+    const long long rm = (long long)ym * nx, rp = (long long)yp * nx;
+    // source of direction a is x - e_a
+    const long long src[Q] = {row + x,  row + xm, rm + x,  row + xp, rp + x,
+                              rm + xm, rm + xp,  rp + xp, rp + xm};
+#pragma unroll
+    for (int a = 0; a < Q; ++a) off[a] = a * N + src[a];
+    if (GEN) {
+      const EdgeSides e(p, x, y, true);
+      if (__builtin_amdgcn_ballot_w64(e.any()) != 0) {
+#pragma unroll
+        for (int a = 1; a < Q; ++a)
+          if (e.wall(p, a)) off[a] = OPs[a] * N + self;
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    fr[a] = Tr::ldr(fin, off[a]);
+    gr[a] = Tr::ldr(gin, off[a]);
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void cook_f(const Shift<P>& sh,
+                                       const typename Prec<P>::R fr[Q],
+                                       typename Prec<P>::C f[Q]) {
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    if constexpr (Prec<P>::shift)
+      f[a] = Prec<P>::cvt(fr[a]) + sh.f(a);
+    else
+      f[a] = Prec<P>::cvt(fr[a]);
+  }
+}
+
+template <int P, bool GEN>
+__device__ __forceinline__ void cook_g(const StepParams& p, const Shift<P>& sh,
+                                       int x, int y,
+                                       const typename Prec<P>::R gr[Q],
+                                       typename Prec<P>::C g[Q]) {
+  using C = typename Prec<P>::C;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    if constexpr (Prec<P>::shift)
+      g[a] = Prec<P>::cvt(gr[a]) + sh.g(a);
+    else
+      g[a] = Prec<P>::cvt(gr[a]);
+  }
+  if (GEN && !p.fresh) {
+    const EdgeSides e(p, x, y, true);
+    if (__builtin_amdgcn_ballot_w64(e.any()) != 0) {
+      const int xm = wrap_or_clamp(x - 1, p.nx, p.perx);
+      const int xp = wrap_or_clamp(x + 1, p.nx, p.perx);
+#pragma unroll
+      for (int a = 1; a < Q; ++a) {
+        const bool ox = e.ox(a), oy = e.oy(a), wall = e.wall(p, a);
+        // source column for the hot-spot test of the y- side
+        const int col = EXs[a] > 0 ? xm : (EXs[a] < 0 ? xp : x);
+        const double Ty =
+            EYs[a] > 0
+                ? (col >= p.hot_x0 && col < p.hot_x1 ? p.T_hot : p.T_bc[2])
+                : p.T_bc[3];
+        const C wT = C(w_rest(a) * (oy ? Ty : p.T_bc[EXs[a] > 0 ? 0 : 1]));
+        g[a] = wall ? C(2) * wT - g[a] : ((ox || oy) ? wT : g[a]);
+      }
+    }
+  }
+}
+
+// Whole pull in one call (the auxiliary kernels).
 template <int P, bool GEN>
 __device__ __forceinline__ void pull_node(
     const StepParams& p, const typename Prec<P>::S* __restrict__ fin,
     const typename Prec<P>::S* __restrict__ gin, int x, int y,
     const Shift<P>& sh,
     typename Prec<P>::C fn[Q], typename Prec<P>::C gn[Q]) {
-  using Tr = Prec<P>;
-  using C = typename Tr::C;
-  const int nx = p.nx, ny = p.ny;
-  const long long N = p.N;
-  const long long row = (long long)y * nx;
-  if (p.fresh) {
-#pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      fn[a] = Tr::ld(fin, a * N + row + x) + sh.f(a);
-      gn[a] = Tr::ld(gin, a * N + row + x) + sh.g(a);
-    }
-    return;
-  }
-  const bool edge = GEN && ((!p.perx && (x == 0 || x == nx - 1)) ||
-                            (!p.pery && (y == 0 || y == ny - 1)));
-  if (!edge) {
-    int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
-    if (xm < 0) xm += nx;
-    if (xp >= nx) xp -= nx;
-    if (ym < 0) ym += ny;
-    if (yp >= ny) yp -= ny;
-    const long long rm = (long long)ym * nx, rp = (long long)yp * nx;
-    // source of direction a is x - e_a
-    const long long src[Q] = {row + x,  row + xm, rm + x,  row + xp, rp + x,
-                              rm + xm, rm + xp,  rp + xp, rp + xm};
-#pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      fn[a] = Tr::ld(fin, a * N + src[a]) + sh.f(a);
-      gn[a] = Tr::ld(gin, a * N + src[a]) + sh.g(a);
-    }
-    return;
-  }
-  constexpr int EXs[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-  constexpr int EYs[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-  constexpr int OPs[Q] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-  const long long self = row + x;
-#pragma unroll
-  for (int a = 0; a < Q; ++a) {
-    Ghost gh = resolve(p, x - EXs[a], y - EYs[a]);
-    if (gh.kind == GH_INSIDE) {
-      const long long s = (long long)gh.y * nx + gh.x;
-      fn[a] = Tr::ld(fin, a * N + s) + sh.f(a);
-      gn[a] = Tr::ld(gin, a * N + s) + sh.g(a);
-    } else if (gh.kind == GH_WALL) {
-      const int o = OPs[a];
-      fn[a] = Tr::ld(fin, o * N + self) + sh.f(o);
-      gn[a] = -(Tr::ld(gin, o * N + self) + sh.g(o)) +
-              C(2.0 * w_rest(a) * gh.T);
-    } else {
-      const long long s = (long long)gh.y * nx + gh.x;
-      fn[a] = Tr::ld(fin, a * N + s) + sh.f(a);
-      gn[a] = C(w_rest(a) * gh.T);
-    }
-  }
+  typename Prec<P>::R fr[Q], gr[Q];
+  pull_raw<P, GEN>(p, fin, gin, x, y, fr, gr);
+  cook_f<P>(sh, fr, fn);
+  cook_g<P, GEN>(p, sh, x, y, gr, gn);
 }
 
 // ------------------------------------------------------- MRT transforms

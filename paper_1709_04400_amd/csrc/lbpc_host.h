@@ -33,7 +33,7 @@ hipError_t launch_phi_in(const StepParams& p, int prec, const double* in,
 int diag_blocks(long long N);
 hipError_t launch_step_batch(const StepParams* table, const void* work,
                              int nwork, int parity, int grid, int prec,
-                             int bw, hipStream_t s);
+                             int bw, hipStream_t s, bool gen = true);
 int work_item_bytes();
 }  // namespace lbpc
 

@@ -78,8 +78,8 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
   const S* __restrict__ gin = static_cast<const S*>(p.gin);
   S* __restrict__ fout = static_cast<S*>(p.fout);
   S* __restrict__ gout = static_cast<S*>(p.gout);
-  const C* __restrict__ phiv = static_cast<const C*>(p.phi);
-  C* __restrict__ phio = static_cast<C*>(p.phi_out);
+  const Gbl<C>* __restrict__ phiv = gbl(static_cast<const C*>(p.phi));
+  Gbl<C>* __restrict__ phio = gbl(static_cast<C*>(p.phi_out));
 
   // column roles
   bool ghostc = false;
@@ -116,12 +116,13 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
     return r < 0 ? r + ny : r - ny;
   };
 
-  // pulled values: row r (loaded one iteration ahead), queues of f (row r-1)
-  // and g (rows r-1, r-2); j (row r-1), T dp/dT (rows r-1, r-2) and 1/rho
-  // (row r-2) of this thread's own column
-  C fc[Q], gc[Q], fq1[Q], gq1[Q], gq2[Q];
+  // pulled values, as loaded (register images): row r (loaded one iteration
+  // ahead), queues of f (row r-1) and g (rows r-1, r-2); j (row r-1),
+  // T dp/dT (rows r-1, r-2) and 1/rho (row r-2) of this thread's own column
+  using R = typename Tr::R;
+  R fc[Q], gc[Q], fq1[Q], gq1[Q], gq2[Q];
 #pragma unroll
-  for (int a = 0; a < Q; ++a) fc[a] = gc[a] = fq1[a] = gq1[a] = gq2[a] = C(0);
+  for (int a = 0; a < Q; ++a) fc[a] = gc[a] = fq1[a] = gq1[a] = gq2[a] = R(0);
   C jx1 = C(0), jy1 = C(0), tdp1 = C(0), tdp2 = C(0), irq = C(0);
 
   // march direction alternates between vertically adjacent row runs, so the
@@ -132,8 +133,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
   const int rfirst = dir > 0 ? Y0 - 2 : Y1 + 1;
   {
     const int rw = wrap_row(rfirst);
-    if (doA && rw >= 0)
-      pull_node<P, GEN>(p, fin, gin, cw, rw, sh, fc, gc);
+    if (doA && rw >= 0) pull_raw<P, GEN>(p, fin, gin, cw, rw, fc, gc);
   }
 
   for (int it = 0; it < nit; ++it) {
@@ -147,13 +147,16 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
     C jxn = C(0), jyn = C(0), tdpn = C(0);
     const int rwA = wrap_row(r);
     if (doA && rwA >= 0) {
-      const C sa = fc[1] + fc[2] + fc[3] + fc[4];
-      const C sd = fc[5] + fc[6] + fc[7] + fc[8];
-      const C rho = fc[0] + sa + sd;
-      jxn = (fc[1] - fc[3]) + (fc[5] - fc[6] - fc[7] + fc[8]);
-      jyn = (fc[2] - fc[4]) + (fc[5] + fc[6] - fc[7] - fc[8]);
-      const C T = gc[0] + (gc[1] + gc[2] + gc[3] + gc[4]) +
-                  (gc[5] + gc[6] + gc[7] + gc[8]);
+      C fa[Q], ga[Q];
+      cook_f<P>(sh, fc, fa);
+      cook_g<P, GEN>(p, sh, cw, rwA, gc, ga);
+      const C sa = fa[1] + fa[2] + fa[3] + fa[4];
+      const C sd = fa[5] + fa[6] + fa[7] + fa[8];
+      const C rho = fa[0] + sa + sd;
+      jxn = (fa[1] - fa[3]) + (fa[5] - fa[6] - fa[7] + fa[8]);
+      jyn = (fa[2] - fa[4]) + (fa[5] + fa[6] - fa[7] - fa[8]);
+      const C T = ga[0] + (ga[1] + ga[2] + ga[3] + ga[4]) +
+                  (ga[5] + ga[6] + ga[7] + ga[8]);
       // Peng-Robinson EOS, Eq. (56), in FP64 with one reciprocal:
       //   p = (rho R T D2 - a th rho^2 D1) / (D1 D2),
       //   T dp/dT = (rho R T D2 + a kappa s sqrt(T/Tc) rho^2 D1) / (D1 D2),
@@ -233,8 +236,9 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
         if (doC && rb >= Y0 && rb < Y1) {
           // flow MRT collision with the forcing scheme of the flow model;
           // |F_m|^2 / psi^2 = G^2 (sx^2 + sy^2), folded into sig1, sig2
-          C m[Q], ms[Q], fo[Q];
-          to_moments(fq1, m);
+          C m[Q], ms[Q], fo[Q], fb[Q];
+          cook_f<P>(sh, fq1, fb);
+          to_moments(fb, m);
           const C v2 = vx * vx + vy * vy;
           C meq[Q];
           meq[0] = rho;
@@ -272,13 +276,12 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
     // f of row r waits one row for its collision; row r + dir is pulled now
 #pragma unroll
     for (int a = 0; a < Q; ++a) fq1[a] = fc[a];
-    C gn[Q];
+    R gn[Q];
 #pragma unroll
-    for (int a = 0; a < Q; ++a) gn[a] = C(0);
+    for (int a = 0; a < Q; ++a) gn[a] = R(0);
     {
       const int rwn = (it + 1 < nit) ? wrap_row(r + dir) : -1;
-      if (doA && rwn >= 0)
-        pull_node<P, GEN>(p, fin, gin, cw, rwn, sh, fc, gn);
+      if (doA && rwn >= 0) pull_raw<P, GEN>(p, fin, gin, cw, rwn, fc, gn);
     }
     __syncthreads();
 
@@ -289,42 +292,47 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
       if (doC && yc >= Y0 && yc < Y1) {
         const C T = s_T[sl2][t];
         const C vx = s_vx[sl2][t], vy = s_vy[sl2][t];
-        // neighbour values (E, W, N, S, NE, NW, SE, SW)
+        // neighbour values (E, W, N, S, NE, NW, SE, SW); a ghost neighbour
+        // across a non-periodic side reads the nearest lattice node (the
+        // LDS column and ring row are clamped), then takes the side
+        // temperature and, across a wall, zero velocity
         C Tn[8], vxn[8], vyn[8], rn[8];
-        const bool edge = GEN && ((!p.perx && (c == 0 || c == nx - 1)) ||
-                                  (!p.pery && (yc == 0 || yc == ny - 1)));
         constexpr int DX[8] = {1, -1, 0, 0, 1, -1, 1, -1};
         constexpr int DY[8] = {0, 0, 1, -1, 1, 1, -1, -1};
-        if (!edge) {
+        const bool r2 = GEN && !p.pery && yc == 0;
+        const bool r3 = GEN && !p.pery && yc == ny - 1;
+        const int sN = r3 ? sl2 : slN, sS = r2 ? sl2 : slS;
 #pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            const int tt = DX[k] > 0 ? ttp : (DX[k] < 0 ? ttm : t);
-            const int sl = DY[k] > 0 ? slN : (DY[k] < 0 ? slS : sl2);
-            Tn[k] = s_T[sl][tt];
-            vxn[k] = s_vx[sl][tt];
-            vyn[k] = s_vy[sl][tt];
-            rn[k] = p.lambda_mode ? s_rho[sl][tt] : C(0);
-          }
-        } else {
+        for (int k = 0; k < 8; ++k) {
+          const int tt = DX[k] > 0 ? ttp : (DX[k] < 0 ? ttm : t);
+          const int sl = DY[k] > 0 ? sN : (DY[k] < 0 ? sS : sl2);
+          Tn[k] = s_T[sl][tt];
+          vxn[k] = s_vx[sl][tt];
+          vyn[k] = s_vy[sl][tt];
+          rn[k] = p.lambda_mode ? s_rho[sl][tt] : C(0);
+        }
+        if (GEN) {
+          const bool c0 = !p.perx && c == 0, c1 = !p.perx && c == nx - 1;
+          if (__builtin_amdgcn_ballot_w64(c0 || c1 || r2 || r3) != 0) {
 #pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            Ghost gh = resolve(p, c + DX[k], yc + DY[k]);
-            // LDS position: unclamped axes keep their offset, clamped ones
-            // fall back to this node's own column / row
-            int tt = t + DX[k];
-            if (!p.perx && (c + DX[k] < 0 || c + DX[k] >= nx)) tt = t;
-            int sl = DY[k] > 0 ? slN : (DY[k] < 0 ? slS : sl2);
-            if (!p.pery && (yc + DY[k] < 0 || yc + DY[k] >= ny)) sl = sl2;
-            rn[k] = s_rho[sl][tt];
-            if (gh.kind == GH_INSIDE) {
-              Tn[k] = s_T[sl][tt];
-              vxn[k] = s_vx[sl][tt];
-              vyn[k] = s_vy[sl][tt];
-            } else {
-              Tn[k] = C(gh.T);
-              const bool wall = gh.kind == GH_WALL;
-              vxn[k] = wall ? C(0) : s_vx[sl][tt];
-              vyn[k] = wall ? C(0) : s_vy[sl][tt];
+            for (int k = 0; k < 8; ++k) {
+              const int xs = DX[k] > 0 ? 1 : 0, ys = DY[k] > 0 ? 3 : 2;
+              const bool ox = DX[k] > 0 ? c1 : (DX[k] < 0 ? c0 : false);
+              const bool oy = DY[k] > 0 ? r3 : (DY[k] < 0 ? r2 : false);
+              const bool wall = (ox && p.bc[xs] == BC_WALL) ||
+                                (oy && p.bc[ys] == BC_WALL);
+              int col = c + DX[k];
+              if (ox) col = c;
+              else if (col < 0) col += nx;
+              else if (col >= nx) col -= nx;
+              const double Ty =
+                  ys == 2 ? (col >= p.hot_x0 && col < p.hot_x1 ? p.T_hot
+                                                                : p.T_bc[2])
+                          : p.T_bc[3];
+              const C Tg = C(oy ? Ty : p.T_bc[xs]);
+              Tn[k] = (ox || oy) ? Tg : Tn[k];
+              vxn[k] = wall ? C(0) : vxn[k];
+              vyn[k] = wall ? C(0) : vyn[k];
             }
           }
         }
@@ -365,8 +373,9 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
         }
         phio[o] = phi;
         // improved thermal MRT collision: Eqs. (45), (46), (53)-(55)
-        C n[Q], ns[Q], go[Q];
-        to_moments(gq2, n);
+        C n[Q], ns[Q], go[Q], gb[Q];
+        cook_g<P, GEN>(p, sh, c, yc, gq2, gb);
+        to_moments(gb, n);
         const C neq4 = -T * vx, neq6 = -T * vy;
         ns[0] = T + S0;
         ns[1] = n[1] - sg[1] * (n[1] + C(2) * T);
@@ -420,7 +429,7 @@ struct WorkItem {
   int c, bx, by, pad;
 };
 
-template <int P, int BLOCK>
+template <int P, int BLOCK, bool GEN>
 __global__ __launch_bounds__(BLOCK) __attribute__((
     amdgpu_waves_per_eu(StepOcc<P>::waves, StepOcc<P>::waves))) void
 k_step_batch(const StepParams* __restrict__ table,
@@ -428,7 +437,7 @@ k_step_batch(const StepParams* __restrict__ table,
   for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
     const WorkItem it = work[w];
     const StepParams& p = table[2 * it.c + parity];
-    step_tile<P, true, BLOCK>(p, it.bx, it.by);
+    step_tile<P, GEN, BLOCK>(p, it.bx, it.by);
     __syncthreads();  // the LDS rings are reused by the next tile
   }
 }
@@ -464,11 +473,15 @@ hipError_t launch_step(const StepParams& p, int prec, hipStream_t s) {
 
 hipError_t launch_step_batch(const StepParams* table, const void* work,
                              int nwork, int parity, int grid, int prec,
-                             int bw, hipStream_t s) {
+                             int bw, hipStream_t s, bool gen) {
   const WorkItem* wk = static_cast<const WorkItem*>(work);
 #define LBPC_BLAUNCH_BW(PR, BW)                                               \
-  hipLaunchKernelGGL((k_step_batch<PR, BW>), dim3(grid), dim3(BW), 0, s,    \
-                     table, wk, nwork, parity);
+  if (gen)                                                                    \
+    hipLaunchKernelGGL((k_step_batch<PR, BW, true>), dim3(grid), dim3(BW), 0, \
+                       s, table, wk, nwork, parity);                          \
+  else                                                                        \
+    hipLaunchKernelGGL((k_step_batch<PR, BW, false>), dim3(grid), dim3(BW),   \
+                       0, s, table, wk, nwork, parity);
 #define LBPC_BLAUNCH(PR)                                                      \
   if (bw == 64) {                                                             \
     LBPC_BLAUNCH_BW(PR, 64)                                                   \
