@@ -22,7 +22,7 @@ SRC_PATH = os.path.join(HERE, "lbpo.c")
 
 BC_PERIODIC, BC_WALL, BC_OPEN = 0, 1, 2
 LAMBDA_CONST, LAMBDA_RHO_CV_CHI = 0, 1
-THERMAL_IMPROVED, THERMAL_COMPROMISED = 0, 1
+THERMAL_IMPROVED, THERMAL_COMPROMISED, THERMAL_GONG_CHENG = 0, 1, 2
 FLAG_FREEZE_FLOW = 1
 FLAG_FREEZE_THERMAL = 2
 FIELDS = {"rho": 0, "T": 1, "ux": 2, "uy": 3, "psi": 4, "Fx": 5, "Fy": 6,
@@ -104,7 +104,7 @@ def lib():
         L.lbpo_matrix_M.restype = None
         L.lbpo_matrix_Minv.argtypes = [dp]
         L.lbpo_matrix_Minv.restype = None
-        for nm in ("lbpo_flow_meq", "lbpo_thermal_meq"):
+        for nm in ("lbpo_flow_meq", "lbpo_thermal_meq", "lbpo_gc_geq"):
             fn = getattr(L, nm)
             fn.argtypes = [ctypes.c_double] * 3 + [dp]
             fn.restype = None
@@ -249,6 +249,13 @@ def flow_meq(rho, vx, vy):
 def thermal_meq(T, vx, vy):
     out = np.empty(9)
     lib().lbpo_thermal_meq(T, vx, vy, _dp(out))
+    return out
+
+
+def gc_geq(T, vx, vy):
+    """Per-direction equilibrium of the Gong-Cheng model, Eq. (14)."""
+    out = np.zeros(9)
+    lib().lbpo_gc_geq(T, vx, vy, _dp(out))
     return out
 
 

@@ -12,6 +12,8 @@
  *                     d_t(phi) taken as a backward difference (Sec. III.B)
  *   6. flow MRT collision with forcing (the cited pseudopotential model)
  *   7. improved thermal MRT collision, Eqs. (45), (46), (53), (54), (55)
+ *      (or, for the Gong-Cheng model, the BGK collision of Eq. (12) with
+ *      the equilibrium of Eq. (14) and the source of Eq. (13))
  *   8. streaming, Eq. (47), with the boundary rules below.
  *
  * Every array is a plain [q][ny][nx] (distributions) or [ny][nx] (fields)
@@ -41,8 +43,11 @@
  *    halfway bounce-back f_a(x) = f*_abar(x) and anti-bounce-back
  *    g_a(x) = -g*_abar(x) + 2 wg_a T_ghost; across an open side,
  *    f_a(x) = f*_a(clamped source) and g_a(x) = wg_a T_ghost.  Here wg is the
- *    rest equilibrium of Eq. (53), wg = M^-1 (1,-2,2,0,...,0).  A wall wins
- *    over an open side at corners.
+ *    rest equilibrium of Eq. (53), wg = M^-1 (1,-2,2,0,...,0), or, for the
+ *    Gong-Cheng model, that of Eq. (14), wg = omega.  A wall wins over an
+ *    open side at corners.
+ *  - Gong-Cheng model: v in Eq. (14) is the flow velocity of step 4, and the
+ *    divergence of Eq. (13) uses the same isotropic differences.
  *  - rho_ave of the buoyancy force is the mean initial density.
  */
 #include "lbpo.h"
@@ -197,6 +202,17 @@ static void mat_vec(const double A[Q][Q], const double *x, double *y) {
   }
 }
 
+/* D2Q9 equilibrium of Eq. (14):
+ * omega_a T [1 + e.v/c_s^2 + (e.v)^2/(2 c_s^4) - v.v/(2 c_s^2)] */
+void lbpo_gc_geq(double T, double vx, double vy, double out[9]) {
+  double v2 = vx * vx + vy * vy;
+  for (int a = 0; a < Q; ++a) {
+    double eu = EX[a] * vx + EY[a] * vy;
+    out[a] = WL[a] * T *
+             (1.0 + eu / CS2 + eu * eu / (2.0 * CS2 * CS2) - v2 / (2.0 * CS2));
+  }
+}
+
 /* ------------------------------------------------------- boundaries -- */
 
 typedef struct {
@@ -280,7 +296,11 @@ static int check_config(const lbpo_config *c) {
       c->lambda_mode != LBPO_LAMBDA_RHO_CV_CHI)
     return LBPO_ERR_ARG;
   if (c->thermal_model != LBPO_THERMAL_IMPROVED &&
-      c->thermal_model != LBPO_THERMAL_COMPROMISED)
+      c->thermal_model != LBPO_THERMAL_COMPROMISED &&
+      c->thermal_model != LBPO_THERMAL_GONG_CHENG)
+    return LBPO_ERR_ARG;
+  if (c->thermal_model == LBPO_THERMAL_GONG_CHENG &&
+      !(c->lambda_mode == LBPO_LAMBDA_CONST ? c->lambda0 > 0.0 : c->chi > 0.0))
     return LBPO_ERR_ARG;
   return LBPO_OK;
 }
@@ -297,7 +317,9 @@ int lbpo_create(const lbpo_config *cfg, lbpo_handle **out) {
   h->ny = cfg->ny;
   h->n = (size_t)cfg->nx * (size_t)cfg->ny;
   build_Minv(h->Minv);
-  {
+  if (cfg->thermal_model == LBPO_THERMAL_GONG_CHENG) {
+    lbpo_gc_geq(1.0, 0.0, 0.0, h->wg);
+  } else {
     double meq[Q];
     lbpo_thermal_meq(1.0, 0.0, 0.0, meq);
     mat_vec((const double(*)[Q])h->Minv, meq, h->wg);
@@ -352,8 +374,12 @@ int lbpo_init_fields(lbpo_handle *h, const double *rho, const double *ux,
     lbpo_flow_meq(rho[i], ux[i], uy[i], meq);
     mat_vec((const double(*)[Q])h->Minv, meq, feq);
     for (int a = 0; a < Q; ++a) h->f[a * h->n + i] = feq[a];
-    lbpo_thermal_meq(T[i], ux[i], uy[i], meq);
-    mat_vec((const double(*)[Q])h->Minv, meq, feq);
+    if (h->c.thermal_model == LBPO_THERMAL_GONG_CHENG) {
+      lbpo_gc_geq(T[i], ux[i], uy[i], feq);
+    } else {
+      lbpo_thermal_meq(T[i], ux[i], uy[i], meq);
+      mat_vec((const double(*)[Q])h->Minv, meq, feq);
+    }
     for (int a = 0; a < Q; ++a) h->g[a * h->n + i] = feq[a];
     sum += rho[i];
   }
@@ -432,7 +458,8 @@ static void interaction_force(const lbpo_handle *h, int x, int y, double *Fx,
   *Fy = -h->c.G * h->psi[i] * sy;
 }
 
-/* step 5: phi of Eq. (28) (underlined terms) at node (x, y) */
+/* step 5: phi of Eq. (28) (underlined terms) at node (x, y); for the
+ * Gong-Cheng model phi of Eq. (13) */
 static double thermal_source(const lbpo_handle *h, int x, int y) {
   const lbpo_config *c = &h->c;
   size_t i = (size_t)y * h->nx + x;
@@ -468,6 +495,8 @@ static double thermal_source(const lbpo_handle *h, int x, int y) {
     dlam_y = c->cv * c->chi * dry;
   }
   double rcv = rho * c->cv;
+  if (c->thermal_model == LBPO_THERMAL_GONG_CHENG)
+    return T * (1.0 - lbpo_dpdT(c, rho, T) / rcv) * divv;
   /* div(lambda grad T) = lambda lap T + grad lambda . grad T */
   double div_lam_gradT = lam * lapT + (dlam_x * dTx + dlam_y * dTy);
   return div_lam_gradT / rcv - h->k_th * lapT +
@@ -556,6 +585,21 @@ static int one_step(lbpo_handle *h) {
                   (1.0 - 0.5 * c->s_f[k]) * S[k];
         mat_vec((const double(*)[Q])h->Minv, ms, fa);
         for (int a = 0; a < Q; ++a) h->fp[a * n + i] = fa[a];
+      }
+
+      if (c->thermal_model == LBPO_THERMAL_GONG_CHENG) {
+        /* step 7 of the Gong-Cheng model: Eq. (12) with G_a = omega_a phi,
+         * g^eq of Eq. (14) and chi = lambda/(rho c_V) = (tau_g - 1/2) c_s^2 */
+        double lam = c->lambda_mode == LBPO_LAMBDA_CONST ? c->lambda0
+                                                         : rho * c->cv * c->chi;
+        double tau = lam / (rho * c->cv * CS2) + 0.5;
+        double geq[Q];
+        lbpo_gc_geq(T, vx, vy, geq);
+        for (int a = 0; a < Q; ++a) {
+          double ga = h->g[a * n + i];
+          h->gp[a * n + i] = ga - (ga - geq[a]) / tau + WL[a] * h->phi[i];
+        }
+        continue;
       }
 
       /* step 7: improved thermal MRT collision */

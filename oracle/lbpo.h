@@ -36,9 +36,18 @@ enum {
 enum { LBPO_BC_PERIODIC = 0, LBPO_BC_WALL = 1, LBPO_BC_OPEN = 2 };
 /* thermal conductivity modes: constant, or lambda = rho c_V chi (Sec. IV) */
 enum { LBPO_LAMBDA_CONST = 0, LBPO_LAMBDA_RHO_CV_CHI = 1 };
-/* thermal models of Sec. IV: the improved one, and the "compromised" one that
- * omits Eqs. (54)-(55) and the 0.5 dt d_t(phi) term of Eq. (46) */
-enum { LBPO_THERMAL_IMPROVED = 0, LBPO_THERMAL_COMPROMISED = 1 };
+/* thermal models: the improved one of Sec. III.B; the "compromised" one of
+ * Sec. IV that omits Eqs. (54)-(55) and the 0.5 dt d_t(phi) term of
+ * Eq. (46); and the Gong-Cheng model of Sec. II.B, Eqs. (11)-(14): BGK
+ * collision with the quadratic equilibrium of Eq. (14), source
+ * G_a = omega_a phi with phi of Eq. (13), and the local relaxation time
+ * tau_g = lambda / (rho c_V c_s^2) + 1/2 that makes chi = lambda/(rho c_V)
+ * = (tau_g - 1/2) c_s^2 (Sec. II.B, below Eq. (25)) */
+enum {
+  LBPO_THERMAL_IMPROVED = 0,
+  LBPO_THERMAL_COMPROMISED = 1,
+  LBPO_THERMAL_GONG_CHENG = 2
+};
 /* test-only flags: flow field frozen (f never changes, F = 0); temperature
  * field frozen (g never changes) */
 enum { LBPO_FLAG_FREEZE_FLOW = 1, LBPO_FLAG_FREEZE_THERMAL = 2 };
@@ -111,6 +120,8 @@ void lbpo_matrix_M(double out[81]);
 void lbpo_matrix_Minv(double out[81]);
 void lbpo_flow_meq(double rho, double vx, double vy, double out[9]);
 void lbpo_thermal_meq(double T, double vx, double vy, double out[9]);
+/* D2Q9 equilibrium of the Gong-Cheng model, Eq. (14), per direction */
+void lbpo_gc_geq(double T, double vx, double vy, double out[9]);
 double lbpo_Tc(double a, double b, double R);
 double lbpo_p_eos(const lbpo_config *cfg, double rho, double T);
 double lbpo_dpdT(const lbpo_config *cfg, double rho, double T);

@@ -201,7 +201,7 @@ def test_isotropic_stencils_exact_on_quadratics(poly):
 
 def _droplet(n=48, R=12.0, **over):
     cfg, fl = I.static_droplet(n, n, R)
-    cfg.update(over)
+    cfg.update(over or {})
     o = O.Oracle(cfg)
     o.init_fields(**fl)
     return o
@@ -286,12 +286,13 @@ def test_save_restore_is_exact():
 
 # ------------------------------------------ temperature equation (Eq. 5) --
 
-def _gauss_run(n, s0, v0, chi, model, steps, axis=0, s_g=None):
+def _gauss_run(n, s0, v0, chi, model, steps, axis=0, s_g=None, over=None):
     """Frozen uniform flow of speed v0 along x (axis 0) or y (axis 1),
     uniform density, Gaussian T pulse."""
     rho0 = I.RHO_L
     cfg = I.base_config(n, n, flags=O.FLAG_FREEZE_FLOW,
                         lambda0=rho0 * I.CV * chi, thermal_model=model)
+    cfg.update(over or {})
     if s_g is not None:
         cfg["s_g"] = list(s_g)
     y, x = np.mgrid[0:n, 0:n].astype(float)
