@@ -71,11 +71,18 @@ typedef enum {
 } lbpc_bc;
 
 typedef enum { LBPC_LAMBDA_CONST = 0, LBPC_LAMBDA_RHO_CV_CHI = 1 } lbpc_lambda;
-/* Sec. IV: the improved model, and the "compromised" one without
+/* The improved model of Sec. III.B; the "compromised" one of Sec. IV without
  * Eqs. (54)-(55) and without the (phi - phi_prev)/2 term */
 typedef enum {
   LBPC_THERMAL_IMPROVED = 0,
-  LBPC_THERMAL_COMPROMISED = 1
+  LBPC_THERMAL_COMPROMISED = 1,
+  /* the Gong-Cheng model of Sec. II.B, Eqs. (11)-(14): BGK collision with the
+   * quadratic equilibrium of Eq. (14), source omega_a phi with phi of
+   * Eq. (13), and the local relaxation time tau_g = lambda/(rho c_V c_s^2)
+   * + 1/2; s_g is not used.  Its side rules use the rest weights omega_a of
+   * Eq. (14) in place of those of Eq. (53).  Needs lambda0 > 0 (constant
+   * conductivity) or chi > 0 (lambda = rho c_V chi). */
+  LBPC_THERMAL_GONG_CHENG = 2
 } lbpc_thermal_model;
 
 /* Ghost rule at a non-periodic side, used by every stencil: a neighbour

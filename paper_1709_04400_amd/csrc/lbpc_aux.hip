@@ -8,8 +8,9 @@ namespace lbpc {
 
 constexpr int AUX_BLOCK = 256;
 
-// f = M^-1 m^eq(rho, u) of the flow model, g = M^-1 m^eq(T, u) of Eq. (53);
-// the host FP64 fields sit in `in` as [rho | ux | uy | T], each of N values.
+// f = M^-1 m^eq(rho, u) of the flow model, g = M^-1 m^eq(T, u) of Eq. (53)
+// (or g = g^eq(T, u) of Eq. (14) for the Gong-Cheng model); the host FP64
+// fields sit in `in` as [rho | ux | uy | T], each of N values.
 template <int P>
 __global__ __launch_bounds__(AUX_BLOCK) void k_init(StepParams p,
                                                     const double* in) {
@@ -38,20 +39,28 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_init(StepParams p,
   for (int a = 0; a < Q; ++a)
     Tr::st(fo, a * N + i,
            typename Tr::C(f[a] - (Tr::shift ? w_lat(a) * p.rho_ref : 0.0)));
-  m[0] = T;
-  m[1] = -2.0 * T;
-  m[2] = 2.0 * T;
-  m[3] = T * vx;
-  m[4] = -T * vx;
-  m[5] = T * vy;
-  m[6] = -T * vy;
-  m[7] = 0.0;
-  m[8] = 0.0;
-  from_moments(m, f);
+  if (p.gc) {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const double eu = EXs[a] * vx + EYs[a] * vy;
+      f[a] = w_lat(a) * T * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * v2);
+    }
+  } else {
+    m[0] = T;
+    m[1] = -2.0 * T;
+    m[2] = 2.0 * T;
+    m[3] = T * vx;
+    m[4] = -T * vx;
+    m[5] = T * vy;
+    m[6] = -T * vy;
+    m[7] = 0.0;
+    m[8] = 0.0;
+    from_moments(m, f);
+  }
 #pragma unroll
   for (int a = 0; a < Q; ++a)
     Tr::st(go, a * N + i,
-           typename Tr::C(f[a] - (Tr::shift ? w_rest(a) * p.T_ref : 0.0)));
+           typename Tr::C(f[a] - (Tr::shift ? w_rest(p, a) * p.T_ref : 0.0)));
 }
 
 // moments at the current time level: out = [rho | jx | jy | T | psi], FP64
@@ -202,7 +211,7 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_load(StepParams p, int which,
   } else {
     S* go = static_cast<S*>(const_cast<void*>(p.gin));
     Tr::st(go, a * N + i,
-           typename Tr::C(in[i] - (Tr::shift ? w_rest(a) * p.T_ref : 0.0)));
+           typename Tr::C(in[i] - (Tr::shift ? w_rest(p, a) * p.T_ref : 0.0)));
   }
 }
 

@@ -37,6 +37,10 @@ struct StepParams {
   double s_g[9];
   double cv, lambda0, chi, k_th;
   int lambda_mode, improved;
+  int gc;                  // Gong-Cheng model (BGK, Eqs. 12-14)
+  double wg0, wg1, wg2;    // rest equilibrium of g per unit T: rest, axis,
+                           // diagonal (Eq. 53, or Eq. 14 for Gong-Cheng)
+  double gc_ta, gc_tb;     // Gong-Cheng: tau_g = gc_ta / rho + gc_tb
   // derived on the host: 1/Tc, 2/G, 1/c_V, lambda0/c_V and the sigma terms
   // 12 sigma G^2 / (1/s_f[k] - 1/2), k = 1, 2 (|F_m|^2/psi^2 = G^2 |s|^2)
   double inv_Tc, two_over_G, inv_cv, lam_over_cv, sig1, sig2;
@@ -123,12 +127,13 @@ template <> struct Prec<3> {  // FP16 deviations, FP32 arithmetic
   }
 };
 
-// D2Q9 weights (shift of f) and rest weights of Eq. (53) (shift of g)
+// D2Q9 weights (shift of f, Eq. 14) and the rest equilibrium of g of the
+// lattice's thermal model (side rules and shift of g)
 __device__ __forceinline__ double w_lat(int a) {
   return a == 0 ? 4.0 / 9.0 : (a < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
 }
-__device__ __forceinline__ double w_rest(int a) {
-  return a == 0 ? 5.0 / 9.0 : 1.0 / 18.0;
+__device__ __forceinline__ double w_rest(const StepParams& p, int a) {
+  return a == 0 ? p.wg0 : (a < 5 ? p.wg1 : p.wg2);
 }
 
 // ---------------------------------------------------------- EOS, Eq. (56)
@@ -211,21 +216,22 @@ __device__ __forceinline__ Ghost resolve(const StepParams& p, int x, int y) {
 }
 
 // Shifts of the shifted storage forms: f is stored as f_a - w_a rho_ref and
-// g as g_a - wg_a T_ref.  Only three f shifts (rest, axis, diagonal) and two
-// g shifts (rest, moving) are distinct; zero for the plain forms.
+// g as g_a - wg_a T_ref.  Three f and three g shifts (rest, axis, diagonal)
+// are distinct; zero for the plain forms.
 template <int P>
 struct Shift {
   using C = typename Prec<P>::C;
-  C f0, f1, f2, g0, g1;
+  C f0, f1, f2, g0, g1, g2;
   __device__ __forceinline__ explicit Shift(const StepParams& p) {
     if constexpr (Prec<P>::shift) {
       f0 = C(w_lat(0) * p.rho_ref);
       f1 = C(w_lat(1) * p.rho_ref);
       f2 = C(w_lat(5) * p.rho_ref);
-      g0 = C(w_rest(0) * p.T_ref);
-      g1 = C(w_rest(1) * p.T_ref);
+      g0 = C(p.wg0 * p.T_ref);
+      g1 = C(p.wg1 * p.T_ref);
+      g2 = C(p.wg2 * p.T_ref);
     } else {
-      f0 = f1 = f2 = g0 = g1 = C(0);
+      f0 = f1 = f2 = g0 = g1 = g2 = C(0);
     }
   }
   __device__ __forceinline__ C f(int a) const {
@@ -234,7 +240,7 @@ struct Shift {
   }
   __device__ __forceinline__ C g(int a) const {
     if constexpr (!Prec<P>::shift) return C(0);
-    return a == 0 ? g0 : g1;
+    return a == 0 ? g0 : (a < 5 ? g1 : g2);
   }
 };
 
@@ -374,7 +380,7 @@ __device__ __forceinline__ void cook_g(const StepParams& p, const Shift<P>& sh,
             EYs[a] > 0
                 ? (col >= p.hot_x0 && col < p.hot_x1 ? p.T_hot : p.T_bc[2])
                 : p.T_bc[3];
-        const C wT = C(w_rest(a) * (oy ? Ty : p.T_bc[EXs[a] > 0 ? 0 : 1]));
+        const C wT = C(w_rest(p, a) * (oy ? Ty : p.T_bc[EXs[a] > 0 ? 0 : 1]));
         g[a] = wall ? C(2) * wT - g[a] : ((ox || oy) ? wT : g[a]);
       }
     }

@@ -124,8 +124,12 @@ inline const char* check_config(const lbpc_config* c) {
       c->lambda_mode != LBPC_LAMBDA_RHO_CV_CHI)
     return "unknown lambda_mode";
   if (c->thermal_model != LBPC_THERMAL_IMPROVED &&
-      c->thermal_model != LBPC_THERMAL_COMPROMISED)
+      c->thermal_model != LBPC_THERMAL_COMPROMISED &&
+      c->thermal_model != LBPC_THERMAL_GONG_CHENG)
     return "unknown thermal_model";
+  if (c->thermal_model == LBPC_THERMAL_GONG_CHENG &&
+      !(c->lambda_mode == LBPC_LAMBDA_CONST ? c->lambda0 > 0.0 : c->chi > 0.0))
+    return "the Gong-Cheng model needs lambda0 > 0 or chi > 0";
   if (c->precision < LBPC_FP64 || c->precision > LBPC_FP16_SHIFTED)
     return "unknown precision";
   return nullptr;
@@ -171,6 +175,26 @@ inline void derive_params(const lbpc_config& c, StepParams& p) {
   p.sig2 = 12.0 * c.sigma * c.G * c.G / (1.0 / c.s_f[2] - 0.5);
   p.lambda_mode = c.lambda_mode;
   p.improved = c.thermal_model == LBPC_THERMAL_IMPROVED;
+  p.gc = c.thermal_model == LBPC_THERMAL_GONG_CHENG;
+  if (p.gc) {
+    // rest equilibrium of Eq. (14): the D2Q9 weights
+    p.wg0 = 4.0 / 9.0;
+    p.wg1 = 1.0 / 9.0;
+    p.wg2 = 1.0 / 36.0;
+    // tau_g = lambda / (rho c_V c_s^2) + 1/2 = gc_ta / rho + gc_tb
+    if (c.lambda_mode == LBPC_LAMBDA_CONST) {
+      p.gc_ta = 3.0 * c.lambda0 / c.cv;
+      p.gc_tb = 0.5;
+    } else {
+      p.gc_ta = 0.0;
+      p.gc_tb = 3.0 * c.chi + 0.5;
+    }
+  } else {
+    // rest equilibrium of Eq. (53): M^-1 (1, -2, 2, 0, ..., 0)
+    p.wg0 = 5.0 / 9.0;
+    p.wg1 = 1.0 / 18.0;
+    p.wg2 = 1.0 / 18.0;
+  }
   p.rho_ref = c.rho_ref;
   p.T_ref = c.T_ref;
   p.N = (long long)c.nx * c.ny;

@@ -16,7 +16,7 @@
 //       pull of row r+1 issued here, in flight during C2
 //       C(r-2) isotropic differences of T, v (and rho) on rows r-3..r-1,
 //              thermal source phi, S0, improved thermal MRT collision of
-//              row r-2, store g*, phi
+//              row r-2 (or the Gong-Cheng BGK collision), store g*, phi
 //     so every pulled value is loaded from memory once per block (halo
 //     columns and the 4 warm-up rows aside) and the 2-hop stencil dependence
 //     (div v needs v one node away, which needs psi two nodes away) never
@@ -352,19 +352,25 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
                        twelfth * ((vyn[4] - vyn[6]) + (vyn[5] - vyn[7]));
         // phi of Eq. (28): div(lambda grad T)/(rho c_V) - k lap T
         //                  + (T - T (dp/dT)/(rho c_V)) div v
-        C lam_term;
-        if (p.lambda_mode == 0) {
-          lam_term = C(p.lam_over_cv) * irq * lapT;
+        C phi;
+        if (p.gc) {
+          // Eq. (13): T (1 - (dp/dT)/(rho c_V)) div v
+          phi = (T - tdp2 * irq * C(p.inv_cv)) * divv;
         } else {
-          // lambda = rho c_V chi: chi (lap T + grad rho . grad T / rho)
-          const C drx = third * (rn[0] - rn[1]) +
-                        twelfth * ((rn[4] - rn[5]) + (rn[6] - rn[7]));
-          const C dry = third * (rn[2] - rn[3]) +
-                        twelfth * ((rn[4] - rn[6]) + (rn[5] - rn[7]));
-          lam_term = C(p.chi) * (lapT + irq * (drx * dTx + dry * dTy));
+          C lam_term;
+          if (p.lambda_mode == 0) {
+            lam_term = C(p.lam_over_cv) * irq * lapT;
+          } else {
+            // lambda = rho c_V chi: chi (lap T + grad rho . grad T / rho)
+            const C drx = third * (rn[0] - rn[1]) +
+                          twelfth * ((rn[4] - rn[5]) + (rn[6] - rn[7]));
+            const C dry = third * (rn[2] - rn[3]) +
+                          twelfth * ((rn[4] - rn[6]) + (rn[5] - rn[7]));
+            lam_term = C(p.chi) * (lapT + irq * (drx * dTx + dry * dTy));
+          }
+          phi = lam_term - C(p.k_th) * lapT +
+                (T - tdp2 * irq * C(p.inv_cv)) * divv;
         }
-        const C phi = lam_term - C(p.k_th) * lapT +
-                      (T - tdp2 * irq * C(p.inv_cv)) * divv;
         const long long o = (long long)yc * nx + c;
         C S0 = phi;
         if (p.improved) {
@@ -372,25 +378,40 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
           S0 = phi + C(0.5) * (phi - prev);
         }
         phio[o] = phi;
-        // improved thermal MRT collision: Eqs. (45), (46), (53)-(55)
-        C n[Q], ns[Q], go[Q], gb[Q];
+        C go[Q], gb[Q];
         cook_g<P, GEN>(p, sh, c, yc, gq2, gb);
-        to_moments(gb, n);
-        const C neq4 = -T * vx, neq6 = -T * vy;
-        ns[0] = T + S0;
-        ns[1] = n[1] - sg[1] * (n[1] + C(2) * T);
-        ns[2] = n[2] - sg[2] * (n[2] - C(2) * T);
-        ns[3] = n[3] - sg[3] * (n[3] - T * vx);
-        ns[4] = n[4] - sg[4] * (n[4] - neq4);
-        ns[5] = n[5] - sg[5] * (n[5] - T * vy);
-        ns[6] = n[6] - sg[6] * (n[6] - neq6);
-        ns[7] = n[7] - sg[7] * n[7];
-        ns[8] = n[8] - sg[8] * n[8];
-        if (p.improved) {
-          ns[3] += (C(1) - C(0.5) * sg[3]) * sg[4] * (n[4] - neq4);
-          ns[5] += (C(1) - C(0.5) * sg[5]) * sg[6] * (n[6] - neq6);
+        if (p.gc) {
+          // Gong-Cheng BGK collision, Eq. (12): g^eq of Eq. (14), source
+          // omega_a phi, tau_g = lambda/(rho c_V c_s^2) + 1/2
+          const C itau = C(1) / (C(p.gc_ta) * irq + C(p.gc_tb));
+          const C base = C(1) - C(1.5) * (vx * vx + vy * vy);
+#pragma unroll
+          for (int a = 0; a < Q; ++a) {
+            const C eu = C(EXs[a]) * vx + C(EYs[a]) * vy;
+            const C wa = C(w_lat(a));
+            const C geq = wa * T * (base + eu * (C(3) + C(4.5) * eu));
+            go[a] = gb[a] - (gb[a] - geq) * itau + wa * phi;
+          }
+        } else {
+          // improved thermal MRT collision: Eqs. (45), (46), (53)-(55)
+          C n[Q], ns[Q];
+          to_moments(gb, n);
+          const C neq4 = -T * vx, neq6 = -T * vy;
+          ns[0] = T + S0;
+          ns[1] = n[1] - sg[1] * (n[1] + C(2) * T);
+          ns[2] = n[2] - sg[2] * (n[2] - C(2) * T);
+          ns[3] = n[3] - sg[3] * (n[3] - T * vx);
+          ns[4] = n[4] - sg[4] * (n[4] - neq4);
+          ns[5] = n[5] - sg[5] * (n[5] - T * vy);
+          ns[6] = n[6] - sg[6] * (n[6] - neq6);
+          ns[7] = n[7] - sg[7] * n[7];
+          ns[8] = n[8] - sg[8] * n[8];
+          if (p.improved) {
+            ns[3] += (C(1) - C(0.5) * sg[3]) * sg[4] * (n[4] - neq4);
+            ns[5] += (C(1) - C(0.5) * sg[5]) * sg[6] * (n[6] - neq6);
+          }
+          from_moments(ns, go);
         }
-        from_moments(ns, go);
 #pragma unroll
         for (int a = 0; a < Q; ++a) Tr::st(gout, a * N + o, go[a] - sh.g(a));
       }

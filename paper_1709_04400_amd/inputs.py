@@ -164,6 +164,19 @@ def heated_droplet(n, radius, T_w_over_Ts, precision=FP64):
     return cfg, droplet_fields(n, n, radius)
 
 
+def d2_droplet(model=THERMAL_IMPROVED, n=200, diameter=60.0,
+               superheat_over_Tc=0.14, precision=FP64):
+    """The droplet-evaporation comparison of Sec. IV.A: an n x n box, a
+    droplet of the given diameter at T_sat in vapour at T_sat, the sides held
+    at T_g = T_sat + superheat (no-slip walls here), constant lambda = 2/3,
+    c_V = 5, nu = 0.1, s_g3 = s_g5 = 1, no gravity; `model` picks the thermal
+    LB model."""
+    Tg = T_SAT + superheat_over_Tc * TC
+    cfg, fl = heated_droplet(n, 0.5 * diameter, Tg / T_SAT, precision)
+    cfg["thermal_model"] = model
+    return cfg, fl
+
+
 def batch_cases(count=256, seed=1709, precision=FP32):
     """The batched evaporation sweep: one heated-wall droplet per draw,
     droplet radius 0.2 x grid size."""
