@@ -23,6 +23,7 @@ SRC_PATH = os.path.join(HERE, "lbpo.c")
 BC_PERIODIC, BC_WALL, BC_OPEN = 0, 1, 2
 LAMBDA_CONST, LAMBDA_RHO_CV_CHI = 0, 1
 THERMAL_IMPROVED, THERMAL_COMPROMISED, THERMAL_GONG_CHENG = 0, 1, 2
+THERMAL_IMPROVED_BGK = 3
 FLAG_FREEZE_FLOW = 1
 FLAG_FREEZE_THERMAL = 2
 FIELDS = {"rho": 0, "T": 1, "ux": 2, "uy": 3, "psi": 4, "Fx": 5, "Fy": 6,
@@ -100,11 +101,14 @@ def lib():
         L.lbpo_set_state.argtypes = [ctypes.c_void_p, dp, dp, dp,
                                      ctypes.c_int32, ctypes.c_double,
                                      ctypes.c_int64]
+        L.lbpo_get_tv_prev.argtypes = [ctypes.c_void_p, dp]
+        L.lbpo_set_tv_prev.argtypes = [ctypes.c_void_p, dp]
         L.lbpo_matrix_M.argtypes = [dp]
         L.lbpo_matrix_M.restype = None
         L.lbpo_matrix_Minv.argtypes = [dp]
         L.lbpo_matrix_Minv.restype = None
-        for nm in ("lbpo_flow_meq", "lbpo_thermal_meq", "lbpo_gc_geq"):
+        for nm in ("lbpo_flow_meq", "lbpo_thermal_meq", "lbpo_gc_geq",
+                   "lbpo_lin_geq"):
             fn = getattr(L, nm)
             fn.argtypes = [ctypes.c_double] * 3 + [dp]
             fn.restype = None
@@ -214,8 +218,11 @@ class Oracle:
             self.h, _dp(f), _dp(g), _dp(ph), ctypes.byref(pv),
             ctypes.byref(ra), ctypes.byref(stp)), "lbpo_get_state")
         assert f.size == 9 * n
+        tv = np.empty((2, self.ny, self.nx))
+        self._check(lib().lbpo_get_tv_prev(self.h, _dp(tv)),
+                    "lbpo_get_tv_prev")
         return {"f": f, "g": g, "phi_prev": ph, "phi_valid": pv.value,
-                "rho_ave": ra.value, "step": stp.value}
+                "rho_ave": ra.value, "step": stp.value, "tv_prev": tv}
 
     def set_state(self, st):
         f = np.ascontiguousarray(st["f"], dtype=np.float64)
@@ -224,6 +231,10 @@ class Oracle:
         self._check(lib().lbpo_set_state(
             self.h, _dp(f), _dp(g), _dp(ph), int(st["phi_valid"]),
             float(st["rho_ave"]), int(st["step"])), "lbpo_set_state")
+        if "tv_prev" in st:
+            tv = np.ascontiguousarray(st["tv_prev"], dtype=np.float64)
+            self._check(lib().lbpo_set_tv_prev(self.h, _dp(tv)),
+                        "lbpo_set_tv_prev")
 
 
 # ---------------------------------------------------------------- pieces --
@@ -256,6 +267,13 @@ def gc_geq(T, vx, vy):
     """Per-direction equilibrium of the Gong-Cheng model, Eq. (14)."""
     out = np.zeros(9)
     lib().lbpo_gc_geq(T, vx, vy, _dp(out))
+    return out
+
+
+def lin_geq(T, vx, vy):
+    """Per-direction equilibrium linear in v, Eq. (29)."""
+    out = np.zeros(9)
+    lib().lbpo_lin_geq(T, vx, vy, _dp(out))
     return out
 
 

@@ -13,7 +13,8 @@
  *   6. flow MRT collision with forcing (the cited pseudopotential model)
  *   7. improved thermal MRT collision, Eqs. (45), (46), (53), (54), (55)
  *      (or, for the Gong-Cheng model, the BGK collision of Eq. (12) with
- *      the equilibrium of Eq. (14) and the source of Eq. (13))
+ *      the equilibrium of Eq. (14) and the source of Eq. (13); or, for the
+ *      BGK form of the improved model, Eq. (33) with Eqs. (29), (31), (32))
  *   8. streaming, Eq. (47), with the boundary rules below.
  *
  * Every array is a plain [q][ny][nx] (distributions) or [ny][nx] (fields)
@@ -44,10 +45,13 @@
  *    g_a(x) = -g*_abar(x) + 2 wg_a T_ghost; across an open side,
  *    f_a(x) = f*_a(clamped source) and g_a(x) = wg_a T_ghost.  Here wg is the
  *    rest equilibrium of Eq. (53), wg = M^-1 (1,-2,2,0,...,0), or, for the
- *    Gong-Cheng model, that of Eq. (14), wg = omega.  A wall wins over an
+ *    BGK models, that of Eq. (14) / Eq. (29), wg = omega.  A wall wins over an
  *    open side at corners.
  *  - Gong-Cheng model: v in Eq. (14) is the flow velocity of step 4, and the
  *    divergence of Eq. (13) uses the same isotropic differences.
+ *  - BGK form of the improved model: d_t(T v) of Eq. (31) is the backward
+ *    difference T v(t) - T v(t - dt) (zero on the first step, as d_t phi),
+ *    and G_a + (dt/2) d_t G_a of Eq. (32) is omega_a S0 with S0 of step 5.
  *  - rho_ave of the buoyancy force is the mean initial density.
  */
 #include "lbpo.h"
@@ -95,6 +99,7 @@ struct lbpo_handle {
   double *fp, *gp;     /* post-collision f*, g* */
   double *rho, *jx, *jy, *T, *psi, *Fx, *Fy, *ux, *uy;
   double *phi, *phi_prev, *S0;
+  double *tvx_prev, *tvy_prev; /* T v of the previous step (BGK form) */
   int phi_valid;
   int initialised;
   int bad;
@@ -213,6 +218,12 @@ void lbpo_gc_geq(double T, double vx, double vy, double out[9]) {
   }
 }
 
+/* D2Q9 equilibrium of Eq. (29): omega_a T (1 + e.v / c_s^2) */
+void lbpo_lin_geq(double T, double vx, double vy, double out[9]) {
+  for (int a = 0; a < Q; ++a)
+    out[a] = WL[a] * T * (1.0 + (EX[a] * vx + EY[a] * vy) / CS2);
+}
+
 /* ------------------------------------------------------- boundaries -- */
 
 typedef struct {
@@ -297,7 +308,8 @@ static int check_config(const lbpo_config *c) {
     return LBPO_ERR_ARG;
   if (c->thermal_model != LBPO_THERMAL_IMPROVED &&
       c->thermal_model != LBPO_THERMAL_COMPROMISED &&
-      c->thermal_model != LBPO_THERMAL_GONG_CHENG)
+      c->thermal_model != LBPO_THERMAL_GONG_CHENG &&
+      c->thermal_model != LBPO_THERMAL_IMPROVED_BGK)
     return LBPO_ERR_ARG;
   if (c->thermal_model == LBPO_THERMAL_GONG_CHENG &&
       !(c->lambda_mode == LBPO_LAMBDA_CONST ? c->lambda0 > 0.0 : c->chi > 0.0))
@@ -317,7 +329,8 @@ int lbpo_create(const lbpo_config *cfg, lbpo_handle **out) {
   h->ny = cfg->ny;
   h->n = (size_t)cfg->nx * (size_t)cfg->ny;
   build_Minv(h->Minv);
-  if (cfg->thermal_model == LBPO_THERMAL_GONG_CHENG) {
+  if (cfg->thermal_model == LBPO_THERMAL_GONG_CHENG ||
+      cfg->thermal_model == LBPO_THERMAL_IMPROVED_BGK) {
     lbpo_gc_geq(1.0, 0.0, 0.0, h->wg);
   } else {
     double meq[Q];
@@ -334,7 +347,7 @@ int lbpo_create(const lbpo_config *cfg, lbpo_handle **out) {
   h->gp = (double *)calloc(Q * n, sizeof(double));
   double **fields[] = {&h->rho, &h->jx, &h->jy, &h->T,   &h->psi,
                        &h->Fx,  &h->Fy, &h->ux, &h->uy,  &h->phi,
-                       &h->phi_prev, &h->S0};
+                       &h->phi_prev, &h->S0, &h->tvx_prev, &h->tvy_prev};
   int ok = h->f && h->g && h->fp && h->gp;
   for (size_t i = 0; i < sizeof(fields) / sizeof(fields[0]); ++i) {
     *fields[i] = (double *)calloc(n, sizeof(double));
@@ -354,6 +367,7 @@ void lbpo_destroy(lbpo_handle *h) {
   free(h->rho); free(h->jx); free(h->jy); free(h->T); free(h->psi);
   free(h->Fx); free(h->Fy); free(h->ux); free(h->uy);
   free(h->phi); free(h->phi_prev); free(h->S0);
+  free(h->tvx_prev); free(h->tvy_prev);
   free(h);
 }
 
@@ -376,6 +390,8 @@ int lbpo_init_fields(lbpo_handle *h, const double *rho, const double *ux,
     for (int a = 0; a < Q; ++a) h->f[a * h->n + i] = feq[a];
     if (h->c.thermal_model == LBPO_THERMAL_GONG_CHENG) {
       lbpo_gc_geq(T[i], ux[i], uy[i], feq);
+    } else if (h->c.thermal_model == LBPO_THERMAL_IMPROVED_BGK) {
+      lbpo_lin_geq(T[i], ux[i], uy[i], feq);
     } else {
       lbpo_thermal_meq(T[i], ux[i], uy[i], meq);
       mat_vec((const double(*)[Q])h->Minv, meq, feq);
@@ -543,8 +559,9 @@ static int one_step(lbpo_handle *h) {
     }
   for (size_t i = 0; i < n; ++i) {
     double prev = h->phi_valid ? h->phi_prev[i] : h->phi[i];
-    if (c->thermal_model == LBPO_THERMAL_IMPROVED)
-      h->S0[i] = h->phi[i] + 0.5 * (h->phi[i] - prev); /* Eq. (46) */
+    if (c->thermal_model == LBPO_THERMAL_IMPROVED ||
+        c->thermal_model == LBPO_THERMAL_IMPROVED_BGK)
+      h->S0[i] = h->phi[i] + 0.5 * (h->phi[i] - prev); /* Eqs. (46), (32) */
     else
       h->S0[i] = h->phi[i];
     sum_S0 += h->S0[i];
@@ -602,6 +619,28 @@ static int one_step(lbpo_handle *h) {
         continue;
       }
 
+      if (c->thermal_model == LBPO_THERMAL_IMPROVED_BGK) {
+        /* step 7 of the BGK form, Eq. (33): BGK relaxation towards Eq. (29),
+         * source G + (dt/2) d_t G = omega_a S0 (Eq. 32) and the correction
+         * C_a = (1 - 1/(2 tau)) omega_a e_a . d_t(T v) / c_s^2 (Eq. 31) */
+        double tau = 1.0 / c->s_g[3];
+        double dtx = 0.0, dty = 0.0;
+        if (h->phi_valid) {
+          dtx = T * vx - h->tvx_prev[i];
+          dty = T * vy - h->tvy_prev[i];
+        }
+        double geq[Q];
+        lbpo_lin_geq(T, vx, vy, geq);
+        for (int a = 0; a < Q; ++a) {
+          double ga = h->g[a * n + i];
+          double Ca = (1.0 - 0.5 / tau) * WL[a] *
+                      (EX[a] * dtx + EY[a] * dty) / CS2;
+          h->gp[a * n + i] =
+              ga - (ga - geq[a]) / tau + WL[a] * h->S0[i] + Ca;
+        }
+        continue;
+      }
+
       /* step 7: improved thermal MRT collision */
       for (int a = 0; a < Q; ++a) fa[a] = h->g[a * n + i];
       mat_vec(MM, fa, m);
@@ -623,6 +662,11 @@ static int one_step(lbpo_handle *h) {
     for (int x = 0; x < h->nx; ++x) stream_node(h, x, y);
 
   memcpy(h->phi_prev, h->phi, n * sizeof(double));
+  if (c->thermal_model == LBPO_THERMAL_IMPROVED_BGK)
+    for (size_t i = 0; i < n; ++i) {
+      h->tvx_prev[i] = h->T[i] * h->ux[i];
+      h->tvy_prev[i] = h->T[i] * h->uy[i];
+    }
   h->phi_valid = 1;
   h->last_sum_S0 = sum_S0;
   h->last_sum_Fx = sum_Fx;
@@ -717,6 +761,20 @@ int lbpo_get_state(lbpo_handle *h, double *f, double *g, double *phi_prev,
   if (phi_valid) *phi_valid = h->phi_valid;
   if (rho_ave) *rho_ave = h->rho_ave;
   if (step) *step = h->step;
+  return LBPO_OK;
+}
+
+int lbpo_get_tv_prev(lbpo_handle *h, double *tv) {
+  if (!h || !tv) return LBPO_ERR_ARG;
+  memcpy(tv, h->tvx_prev, h->n * sizeof(double));
+  memcpy(tv + h->n, h->tvy_prev, h->n * sizeof(double));
+  return LBPO_OK;
+}
+
+int lbpo_set_tv_prev(lbpo_handle *h, const double *tv) {
+  if (!h || !tv) return LBPO_ERR_ARG;
+  memcpy(h->tvx_prev, tv, h->n * sizeof(double));
+  memcpy(h->tvy_prev, tv + h->n, h->n * sizeof(double));
   return LBPO_OK;
 }
 

@@ -46,7 +46,12 @@ enum { LBPO_LAMBDA_CONST = 0, LBPO_LAMBDA_RHO_CV_CHI = 1 };
 enum {
   LBPO_THERMAL_IMPROVED = 0,
   LBPO_THERMAL_COMPROMISED = 1,
-  LBPO_THERMAL_GONG_CHENG = 2
+  LBPO_THERMAL_GONG_CHENG = 2,
+  /* the BGK form of the improved model, Sec. III.A, Eq. (33): equilibrium
+   * of Eq. (29), correction C_a of Eq. (31), source of Eq. (32) with phi of
+   * Eq. (28); one relaxation time tau_g = 1/s_g[3], so k = (tau_g - 1/2)
+   * c_s^2 as in Eq. (41) */
+  LBPO_THERMAL_IMPROVED_BGK = 3
 };
 /* test-only flags: flow field frozen (f never changes, F = 0); temperature
  * field frozen (g never changes) */
@@ -111,6 +116,10 @@ int lbpo_get_diag(lbpo_handle *h, lbpo_diag *out);
 /* canonical state: f(t) [9][ny][nx], g(t) [9][ny][nx], phi(t-1) [ny][nx] */
 int lbpo_get_state(lbpo_handle *h, double *f, double *g, double *phi_prev,
                    int32_t *phi_valid, double *rho_ave, int64_t *step);
+/* history T v(t - dt) of the BGK improved model, [2][ny][nx] (x then y);
+ * zeros for the other models */
+int lbpo_get_tv_prev(lbpo_handle *h, double *tv);
+int lbpo_set_tv_prev(lbpo_handle *h, const double *tv);
 int lbpo_set_state(lbpo_handle *h, const double *f, const double *g,
                    const double *phi_prev, int32_t phi_valid, double rho_ave,
                    int64_t step);
@@ -122,6 +131,8 @@ void lbpo_flow_meq(double rho, double vx, double vy, double out[9]);
 void lbpo_thermal_meq(double T, double vx, double vy, double out[9]);
 /* D2Q9 equilibrium of the Gong-Cheng model, Eq. (14), per direction */
 void lbpo_gc_geq(double T, double vx, double vy, double out[9]);
+/* equilibrium linear in v, Eq. (29), per direction */
+void lbpo_lin_geq(double T, double vx, double vy, double out[9]);
 double lbpo_Tc(double a, double b, double R);
 double lbpo_p_eos(const lbpo_config *cfg, double rho, double T);
 double lbpo_dpdT(const lbpo_config *cfg, double rho, double T);
