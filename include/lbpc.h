@@ -82,7 +82,16 @@ typedef enum {
    * + 1/2; s_g is not used.  Its side rules use the rest weights omega_a of
    * Eq. (14) in place of those of Eq. (53).  Needs lambda0 > 0 (constant
    * conductivity) or chi > 0 (lambda = rho c_V chi). */
-  LBPC_THERMAL_GONG_CHENG = 2
+  LBPC_THERMAL_GONG_CHENG = 2,
+  /* the BGK form of the improved model, Sec. III.A, Eq. (33): BGK relaxation
+   * with tau_g = 1/s_g[3] towards the equilibrium of Eq. (29), the source
+   * omega_a (phi + (phi - phi_prev)/2) of Eq. (32) with phi of Eq. (28), and
+   * the correction of Eq. (31) with d_t(T v) taken as the backward
+   * difference T v(t) - T v(t - 1) (zero on the first step).  It keeps T v
+   * of the previous step per node, which adds 2 values per node to the
+   * workspace and to the saved state.  Side rules use the rest weights
+   * omega_a of Eq. (29). */
+  LBPC_THERMAL_IMPROVED_BGK = 3
 } lbpc_thermal_model;
 
 /* Ghost rule at a non-periodic side, used by every stencil: a neighbour

@@ -375,7 +375,8 @@ lbpc_status lbpc_get_diag(lbpc_handle* h, lbpc_diag* out) {
 lbpc_status lbpc_state_bytes(const lbpc_handle* h, size_t* bytes) {
   if (!h || !bytes) return fail(nullptr, LBPC_ERR_ARG, "NULL argument");
   const size_t N = (size_t)h->cfg.nx * h->cfg.ny;
-  *bytes = 19 * N * sizeof(double) + 3 * sizeof(int64_t);
+  *bytes = (18 + hist_arrays(h->cfg)) * N * sizeof(double) +
+           3 * sizeof(int64_t);
   return LBPC_OK;
 }
 
@@ -398,18 +399,23 @@ lbpc_status lbpc_save_state(lbpc_handle* h, void* host, size_t bytes) {
             "state copy");
     HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
   }
-  HIP_TRY(h, lbpc::launch_phi_out(p, h->cfg.precision, scr, h->stream),
-          "phi copy kernel");
-  HIP_TRY(h,
-          hipMemcpyAsync(dst + 18 * N, scr, N * sizeof(double),
-                         hipMemcpyDeviceToHost, h->stream),
-          "state copy");
-  HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+  const int nh = hist_arrays(h->cfg);
+  for (int k = 0; k < nh; ++k) {
+    StepParams q = p;
+    q.phi = static_cast<char*>(p.phi) + k * N * compute_bytes(h->cfg.precision);
+    HIP_TRY(h, lbpc::launch_phi_out(q, h->cfg.precision, scr, h->stream),
+            "history copy kernel");
+    HIP_TRY(h,
+            hipMemcpyAsync(dst + (18 + k) * N, scr, N * sizeof(double),
+                           hipMemcpyDeviceToHost, h->stream),
+            "state copy");
+    HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+  }
   int64_t meta[3];
   meta[0] = h->phi_valid;
   std::memcpy(&meta[1], &h->rho_ave, sizeof(double));
   meta[2] = h->step;
-  std::memcpy(dst + 19 * N, meta, sizeof(meta));
+  std::memcpy(dst + (18 + nh) * N, meta, sizeof(meta));
   return LBPC_OK;
 }
 
@@ -432,15 +438,20 @@ lbpc_status lbpc_load_state(lbpc_handle* h, const void* host, size_t bytes) {
             "state load kernel");
     HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
   }
-  HIP_TRY(h,
-          hipMemcpyAsync(scr, src + 18 * N, N * sizeof(double),
-                         hipMemcpyHostToDevice, h->stream),
-          "state copy");
-  HIP_TRY(h, lbpc::launch_phi_in(p, h->cfg.precision, scr, h->stream),
-          "phi load kernel");
-  HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+  const int nh = hist_arrays(h->cfg);
+  for (int k = 0; k < nh; ++k) {
+    StepParams q = p;
+    q.phi = static_cast<char*>(p.phi) + k * N * compute_bytes(h->cfg.precision);
+    HIP_TRY(h,
+            hipMemcpyAsync(scr, src + (18 + k) * N, N * sizeof(double),
+                           hipMemcpyHostToDevice, h->stream),
+            "state copy");
+    HIP_TRY(h, lbpc::launch_phi_in(q, h->cfg.precision, scr, h->stream),
+            "history load kernel");
+    HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+  }
   int64_t meta[3];
-  std::memcpy(meta, src + 19 * N, sizeof(meta));
+  std::memcpy(meta, src + (18 + nh) * N, sizeof(meta));
   h->phi_valid = meta[0] != 0;
   std::memcpy(&h->rho_ave, &meta[1], sizeof(double));
   h->step = meta[2];

@@ -9,7 +9,8 @@ namespace lbpc {
 constexpr int AUX_BLOCK = 256;
 
 // f = M^-1 m^eq(rho, u) of the flow model, g = M^-1 m^eq(T, u) of Eq. (53)
-// (or g = g^eq(T, u) of Eq. (14) for the Gong-Cheng model); the host FP64
+// (or g = g^eq(T, u) of Eq. (14) for the Gong-Cheng model, of Eq. (29) for
+// the BGK form of the improved model); the host FP64
 // fields sit in `in` as [rho | ux | uy | T], each of N values.
 template <int P>
 __global__ __launch_bounds__(AUX_BLOCK) void k_init(StepParams p,
@@ -45,6 +46,11 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_init(StepParams p,
       const double eu = EXs[a] * vx + EYs[a] * vy;
       f[a] = w_lat(a) * T * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * v2);
     }
+  } else if (p.bgk) {
+    // Eq. (29)
+#pragma unroll
+    for (int a = 0; a < Q; ++a)
+      f[a] = w_lat(a) * T * (1.0 + 3.0 * (EXs[a] * vx + EYs[a] * vy));
   } else {
     m[0] = T;
     m[1] = -2.0 * T;

@@ -74,10 +74,12 @@ BatchLayout plan_batch(const lbpc_config* cfgs, int n) {
         L.cases[c].dist[b][k] = off;
         off += d;
       }
+    const size_t h =
+        align_up(hist_arrays(cfgs[c]) * N * compute_bytes(cfgs[c].precision));
     L.cases[c].phi = off;
-    off += align_up(N * compute_bytes(cfgs[c].precision));
+    off += h;
     L.cases[c].tune_phi = off;
-    off += align_up(N * compute_bytes(cfgs[c].precision));
+    off += h;
   }
   L.total = off;
   return L;

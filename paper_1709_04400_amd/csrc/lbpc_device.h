@@ -38,6 +38,9 @@ struct StepParams {
   double cv, lambda0, chi, k_th;
   int lambda_mode, improved;
   int gc;                  // Gong-Cheng model (BGK, Eqs. 12-14)
+  int bgk;                 // BGK form of the improved model (Eq. 33)
+  double bgk_itau;         // its 1/tau_g
+  double bgk_cfac;         // (1 - 1/(2 tau_g)) / c_s^2 of Eq. (31)
   double wg0, wg1, wg2;    // rest equilibrium of g per unit T: rest, axis,
                            // diagonal (Eq. 53, or Eq. 14 for Gong-Cheng)
   double gc_ta, gc_tb;     // Gong-Cheng: tau_g = gc_ta / rho + gc_tb
@@ -54,8 +57,10 @@ struct StepParams {
   const void* gin;
   void* fout;       // [9][N] output f*(t)
   void* gout;
-  void* phi;        // [N] phi(t-1) in (compute precision)
-  void* phi_out;    // [N] phi(t) out; the same array except while tuning
+  void* phi;        // [N] phi(t-1) (compute precision); for the BGK form
+                    // followed by [N] T v_x and [N] T v_y of step t-1
+  void* phi_out;    // the same for step t; the same arrays except while
+                    // the autotuner times steps
   long long N;      // nx * ny
 };
 

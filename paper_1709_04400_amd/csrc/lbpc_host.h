@@ -48,6 +48,11 @@ inline size_t store_bytes(int prec) {
   return prec == LBPC_FP64 ? 8 : (prec == LBPC_FP16_SHIFTED ? 2 : 4);
 }
 inline size_t compute_bytes(int prec) { return prec == LBPC_FP64 ? 8 : 4; }
+// per-node history arrays (compute precision): phi(t-1), and for the BGK
+// form of the improved model also T v_x and T v_y of the previous step
+inline int hist_arrays(const lbpc_config& c) {
+  return c.thermal_model == LBPC_THERMAL_IMPROVED_BGK ? 3 : 1;
+}
 
 struct Layout {
   size_t dist[2][2];  // offsets of f / g of buffer 0 / 1
@@ -68,8 +73,9 @@ inline Layout plan(const lbpc_config& c) {
       L.dist[b][k] = off;
       off += dbytes;
     }
+  const size_t hbytes = align_up(hist_arrays(c) * N * compute_bytes(c.precision));
   L.phi = off;
-  off += align_up(N * compute_bytes(c.precision));
+  off += hbytes;
   L.scratch = off;
   off += align_up(5 * N * sizeof(double));
   L.partial = off;
@@ -83,7 +89,7 @@ inline Layout plan(const lbpc_config& c) {
   L.work = off;
   off += align_up(L.work_capacity * 16);
   L.tune_phi = off;
-  off += align_up(N * compute_bytes(c.precision));
+  off += hbytes;
   L.total = off;
   return L;
 }
@@ -125,7 +131,8 @@ inline const char* check_config(const lbpc_config* c) {
     return "unknown lambda_mode";
   if (c->thermal_model != LBPC_THERMAL_IMPROVED &&
       c->thermal_model != LBPC_THERMAL_COMPROMISED &&
-      c->thermal_model != LBPC_THERMAL_GONG_CHENG)
+      c->thermal_model != LBPC_THERMAL_GONG_CHENG &&
+      c->thermal_model != LBPC_THERMAL_IMPROVED_BGK)
     return "unknown thermal_model";
   if (c->thermal_model == LBPC_THERMAL_GONG_CHENG &&
       !(c->lambda_mode == LBPC_LAMBDA_CONST ? c->lambda0 > 0.0 : c->chi > 0.0))
@@ -176,13 +183,20 @@ inline void derive_params(const lbpc_config& c, StepParams& p) {
   p.lambda_mode = c.lambda_mode;
   p.improved = c.thermal_model == LBPC_THERMAL_IMPROVED;
   p.gc = c.thermal_model == LBPC_THERMAL_GONG_CHENG;
-  if (p.gc) {
-    // rest equilibrium of Eq. (14): the D2Q9 weights
+  p.bgk = c.thermal_model == LBPC_THERMAL_IMPROVED_BGK;
+  // BGK form: 1/tau_g = s_g[3]; (1 - 1/(2 tau_g)) / c_s^2 of Eq. (31)
+  p.bgk_itau = c.s_g[3];
+  p.bgk_cfac = 3.0 * (1.0 - 0.5 * c.s_g[3]);
+  if (p.gc || p.bgk) {
+    // rest equilibrium of Eqs. (14) and (29): the D2Q9 weights
     p.wg0 = 4.0 / 9.0;
     p.wg1 = 1.0 / 9.0;
     p.wg2 = 1.0 / 36.0;
     // tau_g = lambda / (rho c_V c_s^2) + 1/2 = gc_ta / rho + gc_tb
-    if (c.lambda_mode == LBPC_LAMBDA_CONST) {
+    if (!p.gc) {
+      p.gc_ta = 0.0;
+      p.gc_tb = 0.0;
+    } else if (c.lambda_mode == LBPC_LAMBDA_CONST) {
       p.gc_ta = 3.0 * c.lambda0 / c.cv;
       p.gc_tb = 0.5;
     } else {

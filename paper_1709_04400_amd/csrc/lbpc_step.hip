@@ -16,7 +16,8 @@
 //       pull of row r+1 issued here, in flight during C2
 //       C(r-2) isotropic differences of T, v (and rho) on rows r-3..r-1,
 //              thermal source phi, S0, improved thermal MRT collision of
-//              row r-2 (or the Gong-Cheng BGK collision), store g*, phi
+//              row r-2 (or a BGK collision: the Gong-Cheng model, or the
+//              BGK form of the improved model), store g*, phi
 //     so every pulled value is loaded from memory once per block (halo
 //     columns and the 4 warm-up rows aside) and the 2-hop stencil dependence
 //     (div v needs v one node away, which needs psi two nodes away) never
@@ -373,24 +374,46 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
         }
         const long long o = (long long)yc * nx + c;
         C S0 = phi;
-        if (p.improved) {
+        if (p.improved || p.bgk) {
           const C prev = p.phi_valid ? phiv[o] : phi;
           S0 = phi + C(0.5) * (phi - prev);
         }
         phio[o] = phi;
         C go[Q], gb[Q];
         cook_g<P, GEN>(p, sh, c, yc, gq2, gb);
-        if (p.gc) {
-          // Gong-Cheng BGK collision, Eq. (12): g^eq of Eq. (14), source
-          // omega_a phi, tau_g = lambda/(rho c_V c_s^2) + 1/2
-          const C itau = C(1) / (C(p.gc_ta) * irq + C(p.gc_tb));
-          const C base = C(1) - C(1.5) * (vx * vx + vy * vy);
+        if (p.gc || p.bgk) {
+          // BGK collisions.  Gong-Cheng, Eq. (12): g^eq of Eq. (14), source
+          // omega_a phi, tau_g = lambda/(rho c_V c_s^2) + 1/2.  BGK form of
+          // the improved model, Eq. (33): g^eq of Eq. (29), source
+          // omega_a S0 (Eq. 32) and the correction of Eq. (31) with
+          // d_t(T v) = T v(t) - T v(t-1) (history after phi in the array)
+          C itau, base, q2, src, cf = C(0), dx = C(0), dy = C(0);
+          if (p.gc) {
+            itau = C(1) / (C(p.gc_ta) * irq + C(p.gc_tb));
+            base = C(1) - C(1.5) * (vx * vx + vy * vy);
+            q2 = C(4.5);
+            src = phi;
+          } else {
+            itau = C(p.bgk_itau);
+            base = C(1);
+            q2 = C(0);
+            src = S0;
+            cf = C(p.bgk_cfac);
+            const C tvx = T * vx, tvy = T * vy;
+            if (p.phi_valid) {
+              dx = tvx - phiv[N + o];
+              dy = tvy - phiv[2 * N + o];
+            }
+            phio[N + o] = tvx;
+            phio[2 * N + o] = tvy;
+          }
 #pragma unroll
           for (int a = 0; a < Q; ++a) {
             const C eu = C(EXs[a]) * vx + C(EYs[a]) * vy;
             const C wa = C(w_lat(a));
-            const C geq = wa * T * (base + eu * (C(3) + C(4.5) * eu));
-            go[a] = gb[a] - (gb[a] - geq) * itau + wa * phi;
+            const C geq = wa * T * (base + eu * (C(3) + q2 * eu));
+            go[a] = gb[a] - (gb[a] - geq) * itau + wa * src +
+                    cf * wa * (C(EXs[a]) * dx + C(EYs[a]) * dy);
           }
         } else {
           // improved thermal MRT collision: Eqs. (45), (46), (53)-(55)

@@ -1,0 +1,154 @@
+"""The BGK form of the improved model (Sec. III.A, Eq. 33) on the GPU.
+
+FP64 parity with the CPU oracle through the C ABI (periodic, walled with a
+hot spot and lambda = rho c_V chi, open sides, inside a batch that mixes all
+four thermal models), the extra T v history through save / load and the
+autotuner, reduced-precision short runs, and the droplet-evaporation run of
+Sec. IV.A next to the MRT form.
+"""
+import json
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1709_04400_amd import inputs as I
+from test_gpu_parity import _assert_ok, _errors, run_pair
+
+pytestmark = pytest.mark.gpu
+BGK = I.THERMAL_IMPROVED_BGK
+
+
+def _lb():
+    from paper_1709_04400_amd import lbpc
+    return lbpc
+
+
+def _rates(s3):
+    s_g = [1.0] * 9
+    s_g[3] = s_g[5] = s3
+    return s_g
+
+
+def test_bgk_periodic_droplet():
+    cfg, fl = I.static_droplet(64, 64, 16.0)
+    cfg.update(thermal_model=BGK, gy=-2e-5, s_g=_rates(1.2))
+    _assert_ok(run_pair(cfg, fl, 800, chunks=2))
+
+
+def test_bgk_walls_hot_spot_lambda_rho_cv_chi():
+    cfg, fl = I.bubble(nx=96, ny=112, pool=80, hot_width=14, g=3e-5)
+    # tau = 1/1.6 keeps k = (tau - 1/2)/3 below chi = 0.06; with k > chi the
+    # -(k - chi) lap T part of phi (Eq. 28) is unstable here (in the oracle
+    # too)
+    cfg.update(thermal_model=BGK, s_g=_rates(1.6))
+    _assert_ok(run_pair(cfg, fl, 800, chunks=2))
+
+
+def test_bgk_open_and_mixed_sides():
+    cfg, fl = I.evaporation(96, 16.0, 1.1)
+    cfg.update(thermal_model=BGK,
+               bc=[I.BC_WALL, I.BC_WALL, I.BC_OPEN, I.BC_OPEN],
+               T_bc=[1.05 * I.T_SAT, 1.02 * I.T_SAT, 1.1 * I.T_SAT,
+                     1.0 * I.T_SAT])
+    _assert_ok(run_pair(cfg, fl, 600, chunks=2))
+
+
+def test_all_four_models_in_one_batch():
+    cases = []
+    for model, n in ((I.THERMAL_IMPROVED, 72), (I.THERMAL_COMPROMISED, 56),
+                     (I.THERMAL_GONG_CHENG, 64), (BGK, 80), (BGK, 48)):
+        c, f = I.heated_droplet(n, 0.2 * n, 1.12)
+        c["thermal_model"] = model
+        cases.append((c, f))
+    cases[-1][0]["bc"] = [I.BC_PERIODIC] * 4
+    b = _lb().Batch([c for c, _ in cases])
+    for k, (_, f) in enumerate(cases):
+        b.init_fields(k, f["rho"], f["ux"], f["uy"], f["T"])
+    b.step(301)
+    for k, (cfg, f) in enumerate(cases):
+        o = O.Oracle(cfg)
+        o.init_fields(**f)
+        o.step(301)
+        e = _errors(b.rho_u_T(k), o.rho_u_T())
+        assert e["rho"] < 1e-11 and e["T"] < 1e-11 and e["u"] < 1e-11, (k, e)
+    b.close()
+
+
+def test_bgk_save_load_keeps_the_history():
+    cfg, fl = I.heated_droplet(64, 12.0, 1.15)
+    cfg.update(thermal_model=BGK, gy=-2e-5)
+    g = _lb().Simulation(cfg)
+    g.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
+    g.step(37)
+    st = g.save_state()
+    g.step(20)
+    ref = g.rho_u_T()
+    g.close()
+    g2 = _lb().Simulation(cfg)
+    g2.load_state(st)
+    g2.step(20)
+    for a, b in zip(ref, g2.rho_u_T()):
+        assert np.array_equal(a, b)
+    g2.close()
+    # the saved state continues the oracle's run to the parity bar
+    o = O.Oracle(cfg)
+    o.init_fields(**fl)
+    o.step(57)
+    _assert_ok([_errors(ref, o.rho_u_T())])
+
+
+def test_bgk_autotune_leaves_the_state():
+    cfg, fl = I.heated_droplet(96, 18.0, 1.15)
+    cfg["thermal_model"] = BGK
+    runs = []
+    for tune in (False, True):
+        g = _lb().Simulation(cfg)
+        g.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
+        g.step(25)
+        if tune:
+            g.autotune(2)
+        g.step(25)
+        runs.append(g.rho_u_T())
+        g.close()
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
+
+
+# bounds about three times the errors measured when they were set
+BGK_SHORT = {I.FP32: 3e-5, I.FP32_SHIFTED: 3e-5, I.FP16_SHIFTED: 2e-2}
+
+
+@pytest.mark.parametrize("prec", [I.FP32, I.FP32_SHIFTED, I.FP16_SHIFTED])
+def test_bgk_reduced_precision_short_run(prec):
+    cfg, fl = I.heated_droplet(64, 14.0, 1.1)
+    cfg["thermal_model"] = BGK
+    o = O.Oracle(cfg)
+    o.init_fields(**fl)
+    o.step(200)
+    cfg["precision"] = prec
+    g = _lb().Simulation(cfg)
+    g.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
+    g.step(200)
+    e = _errors(g.rho_u_T(), o.rho_u_T())
+    g.close()
+    print("\n[precision] " + json.dumps({"result": "bgk_short_run",
+                                          "precision": prec, **e}), flush=True)
+    assert e["rho"] < BGK_SHORT[prec] and e["T"] < BGK_SHORT[prec], e
+
+
+def test_bgk_form_obeys_the_d2_law():
+    """Sec. IV.A set-up: the BGK form removes the same error terms as the
+    MRT improved model.  Its (D/D0)^2 falls linearly after the start-up
+    transient (loss per 4000 steps constant within 15 %) and stays within
+    0.03 of the MRT form over 40000 steps (measured: 0.018, the BGK form
+    evaporating slightly faster; the two estimate d_t(T v) differently)."""
+    from test_gpu_gc import _d2_history
+    imp = _d2_history(I.THERMAL_IMPROVED, 40000, 4000)
+    bgk = _d2_history(BGK, 40000, 4000)
+    print("\n[d2] " + json.dumps({"improved": [round(float(v), 4) for v in imp],
+                                   "bgk": [round(float(v), 4) for v in bgk]}),
+          flush=True)
+    d = -np.diff(bgk[4:])
+    assert np.all(d > 0) and d.max() < 1.15 * d.min()
+    assert np.abs(imp - bgk).max() < 0.03
