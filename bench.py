@@ -31,10 +31,11 @@ PREC_NAME = {0: "FP64", 1: "FP32", 2: "FP32_SHIFTED", 3: "FP16_SHIFTED"}
 PREC_DTYPE = {0: "f64", 1: "f32", 2: "f32", 3: "f16-storage/f32"}
 
 
-def gpu_run(n, prec, steps, warmup, per_launch=40):
+def gpu_run(n, prec, steps, warmup, per_launch=40, model=0):
     import torch
     from paper_1709_04400_amd import inputs, lbpc
     cfg, fl = inputs.spinodal(n, precision=prec)
+    cfg["thermal_model"] = model
     sim = lbpc.Simulation(cfg)
     sim.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
     del fl
@@ -179,6 +180,24 @@ def main():
                 "alg_GBs": round(vb, 1),
                 "frac": round(vb / HBM_PEAK_GBS, 4),
                 "bytes_per_lup": BYTES_PER_LUP[prec]}
+        # the other thermal models on the same workload (FP64): the
+        # Gong-Cheng BGK collision, and the BGK form of the improved model,
+        # which also reads and writes T v of the previous step
+        for model, name, bpl in ((2, "GONG_CHENG_FP64", BYTES_PER_LUP[0]),
+                                 (3, "IMPROVED_BGK_FP64",
+                                  BYTES_PER_LUP[0] + 4 * 8)):
+            try:
+                vms, vk, _ = gpu_run(args.n, 0, max(args.steps // 8, 50),
+                                     args.warmup, model=model)
+            except RuntimeError as e:
+                var[name] = {"error": str(e)}
+                continue
+            vb = bpl * nodes / (vk * 1e-3) / 1e9
+            var[name] = {
+                "MLUPS": round(nodes / vms / 1e3, 1),
+                "ms_per_step": round(vms, 5), "dtype": "f64",
+                "alg_GBs": round(vb, 1), "frac": round(vb / HBM_PEAK_GBS, 4),
+                "bytes_per_lup": bpl}
         out["variants"] = var
     if args.batch:
         bsteps = max(args.steps // 10, 50)

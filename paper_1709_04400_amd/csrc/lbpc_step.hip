@@ -26,6 +26,8 @@
 // Non-periodic sides: the pull applies bounce-back / open rules at edge
 // nodes, and LDS reads of a ghost neighbour take the nearest lattice node's
 // values with the ghost temperature / velocity rule.
+#include <type_traits>
+
 #include "lbpc_device.h"
 
 namespace lbpc {
@@ -50,9 +52,14 @@ __device__ __forceinline__ void block_tile(const StepParams& p, int& bx,
   bx = b - by * p.nbx;
 }
 
-// waves per SIMD the register budget is sized for: the FP64 form holds its
-// queues of pulled values in 64-bit registers
-template <int P> struct StepOcc { static constexpr int waves = P == 0 ? 2 : 3; };
+// waves per SIMD the register budget is sized for (the FP64 form holds its
+// queues of pulled values in 64-bit registers), and how many rows ahead the
+// pull runs: 1 for FP64, 2 for the FP32 forms (their g queue sits in LDS,
+// for which FP64 has no room)
+template <int P> struct StepOcc {
+  static constexpr int waves = P == 0 ? 2 : 3;
+  static constexpr int prefetch = P == 0 ? 1 : 2;
+};
 
 // One tile: strip bx (W columns + halo), row run by (H rows), of the lattice
 // described by p.
@@ -111,19 +118,45 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
   }
 
   // row r -> wrapped row, or -1 for a ghost row of a non-periodic y side
+  // Pulls are issued by every lane and every iteration, whether or not the
+  // row is used: lanes and rows without a node of their own read a clamped
+  // node, and the values are never used.  With no branch around the loads
+  // the compiler's wait counts follow only the loads actually in flight.
+  const int cl = cw < 0 ? 0 : (cw >= nx ? nx - 1 : cw);
+  auto pull_row = [&](int rw, typename Tr::R* fr, typename Tr::R* gr) {
+    pull_raw<P, GEN>(p, fin, gin, cl, rw < 0 ? Y0 : rw, fr, gr);
+  };
+
   auto wrap_row = [&](int r) -> int {
     if (r >= 0 && r < ny) return r;
     if (!p.pery) return -1;
     return r < 0 ? r + ny : r - ny;
   };
 
-  // pulled values, as loaded (register images): row r (loaded one iteration
-  // ahead), queues of f (row r-1) and g (rows r-1, r-2); j (row r-1),
-  // T dp/dT (rows r-1, r-2) and 1/rho (row r-2) of this thread's own column
+  // Pulled values stay as loaded (register images) until they are used, so
+  // the loads of a row run while earlier rows are computed.
+  //  PD = 1: row r is loaded one iteration ahead into slot 0 of F / G; f
+  //    waits one more row in fq1 for the flow collision, g two rows in
+  //    gq1, gq2 for the thermal collision.
+  //  PD = 2: rows r+1 and r+2 are in flight in a 3-slot ring F / G (slot =
+  //    iteration mod 3; the loop is unrolled by 3 so every slot is a set of
+  //    registers and no in-flight load is ever moved); F keeps row r for
+  //    the flow collision of the next iteration, and the thermal collision
+  //    two rows later reads g of its row, as cooked at A, from a per-thread
+  //    LDS ring.
+  // Also carried: j (row r-1), T dp/dT (rows r-1, r-2) and 1/rho (row r-2)
+  // of this thread's own column.
+  constexpr int PD = StepOcc<P>::prefetch;
+  constexpr int NS = PD == 1 ? 1 : 3;
   using R = typename Tr::R;
-  R fc[Q], gc[Q], fq1[Q], gq1[Q], gq2[Q];
+  R F[NS][Q], G[NS][Q], fq1[Q], gq1[Q], gq2[Q];
 #pragma unroll
-  for (int a = 0; a < Q; ++a) fc[a] = gc[a] = fq1[a] = gq1[a] = gq2[a] = R(0);
+  for (int a = 0; a < Q; ++a) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) F[k][a] = G[k][a] = R(0);
+    fq1[a] = gq1[a] = gq2[a] = R(0);
+  }
+  __shared__ C s_g[PD == 2 ? 3 : 1][PD == 2 ? Q : 1][PD == 2 ? BLOCK : 1];
   C jx1 = C(0), jy1 = C(0), tdp1 = C(0), tdp2 = C(0), irq = C(0);
 
   // march direction alternates between vertically adjacent row runs, so the
@@ -132,12 +165,17 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
   const int dir = (by & 1) ? -1 : 1;
   const int nit = Y1 - Y0 + 4;
   const int rfirst = dir > 0 ? Y0 - 2 : Y1 + 1;
-  {
-    const int rw = wrap_row(rfirst);
-    if (doA && rw >= 0) pull_raw<P, GEN>(p, fin, gin, cw, rw, fc, gc);
+#pragma unroll
+  for (int k = 0; k < PD; ++k) {
+    const int rw = wrap_row(rfirst + k * dir);
+    pull_row(rw, F[k], G[k]);
   }
 
-  for (int it = 0; it < nit; ++it) {
+  // one iteration; kc is the ring slot of row r (always 0 for PD = 1)
+  auto iteration = [&](auto kc, const int it) __attribute__((always_inline)) {
+    constexpr int k = decltype(kc)::value;
+    constexpr int kp = PD == 1 ? 0 : (k + 2) % 3;  // row r-1, then row r+2
+    constexpr int k2 = PD == 1 ? 0 : (k + 1) % 3;  // g ring: row r-2
     const int r = rfirst + dir * it;
     const int sl0 = it % RING;                // slot of row r
     const int sl1 = (it + RING - 1) % RING;   // row r - dir
@@ -149,8 +187,12 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
     const int rwA = wrap_row(r);
     if (doA && rwA >= 0) {
       C fa[Q], ga[Q];
-      cook_f<P>(sh, fc, fa);
-      cook_g<P, GEN>(p, sh, cw, rwA, gc, ga);
+      cook_f<P>(sh, F[k], fa);
+      cook_g<P, GEN>(p, sh, cw, rwA, G[k], ga);
+      if constexpr (PD == 2) {
+#pragma unroll
+        for (int a = 0; a < Q; ++a) s_g[k][a][t] = ga[a];
+      }
       const C sa = fa[1] + fa[2] + fa[3] + fa[4];
       const C sd = fa[5] + fa[6] + fa[7] + fa[8];
       const C rho = fa[0] + sa + sd;
@@ -238,7 +280,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
           // flow MRT collision with the forcing scheme of the flow model;
           // |F_m|^2 / psi^2 = G^2 (sx^2 + sy^2), folded into sig1, sig2
           C m[Q], ms[Q], fo[Q], fb[Q];
-          cook_f<P>(sh, fq1, fb);
+          cook_f<P>(sh, PD == 1 ? fq1 : F[kp], fb);
           to_moments(fb, m);
           const C v2 = vx * vx + vy * vy;
           C meq[Q];
@@ -274,15 +316,37 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
         }
       }
     }
-    // f of row r waits one row for its collision; row r + dir is pulled now
-#pragma unroll
-    for (int a = 0; a < Q; ++a) fq1[a] = fc[a];
-    R gn[Q];
-#pragma unroll
-    for (int a = 0; a < Q; ++a) gn[a] = R(0);
+    // history of the row C2 updates below (phi(t-1), and T v(t-1) of the
+    // BGK form), loaded before the row prefetch: loads complete in order,
+    // so waiting for a load issued after the prefetch would wait for the
+    // whole prefetch as well
+    C hphi = C(0), htx = C(0), hty = C(0);
     {
+      const int yc = r - 2 * dir;
+      if (doC && yc >= Y0 && yc < Y1 && p.phi_valid &&
+          (p.improved || p.bgk)) {
+        const long long o = (long long)yc * nx + c;
+        hphi = phiv[o];
+        if (p.bgk) {
+          htx = phiv[N + o];
+          hty = phiv[2 * N + o];
+        }
+      }
+    }
+    R gn[Q];
+    if constexpr (PD == 1) {
+      // f of row r waits one row for its collision; row r + dir is pulled
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        fq1[a] = F[0][a];
+        gn[a] = R(0);
+      }
       const int rwn = (it + 1 < nit) ? wrap_row(r + dir) : -1;
-      if (doA && rwn >= 0) pull_raw<P, GEN>(p, fin, gin, cw, rwn, fc, gn);
+      pull_row(rwn, F[0], gn);
+    } else {
+      // row r + 2 dir into the slot row r - 1 has just left
+      const int rwn = (it + 2 < nit) ? wrap_row(r + 2 * dir) : -1;
+      pull_row(rwn, F[kp], G[kp]);
     }
     __syncthreads();
 
@@ -375,12 +439,17 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
         const long long o = (long long)yc * nx + c;
         C S0 = phi;
         if (p.improved || p.bgk) {
-          const C prev = p.phi_valid ? phiv[o] : phi;
+          const C prev = p.phi_valid ? hphi : phi;
           S0 = phi + C(0.5) * (phi - prev);
         }
         phio[o] = phi;
         C go[Q], gb[Q];
-        cook_g<P, GEN>(p, sh, c, yc, gq2, gb);
+        if constexpr (PD == 1) {
+          cook_g<P, GEN>(p, sh, c, yc, gq2, gb);
+        } else {
+#pragma unroll
+          for (int a = 0; a < Q; ++a) gb[a] = s_g[k2][a][t];
+        }
         if (p.gc || p.bgk) {
           // BGK collisions.  Gong-Cheng, Eq. (12): g^eq of Eq. (14), source
           // omega_a phi, tau_g = lambda/(rho c_V c_s^2) + 1/2.  BGK form of
@@ -401,8 +470,8 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
             cf = C(p.bgk_cfac);
             const C tvx = T * vx, tvy = T * vy;
             if (p.phi_valid) {
-              dx = tvx - phiv[N + o];
-              dy = tvy - phiv[2 * N + o];
+              dx = tvx - htx;
+              dy = tvy - hty;
             }
             phio[N + o] = tvx;
             phio[2 * N + o] = tvy;
@@ -440,18 +509,35 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
       }
     }
 
-    // rotate the per-column queues
+    if constexpr (PD == 1) {
+      // rotate the per-column g queue
 #pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      gq2[a] = gq1[a];
-      gq1[a] = gc[a];
-      gc[a] = gn[a];
+      for (int a = 0; a < Q; ++a) {
+        gq2[a] = gq1[a];
+        gq1[a] = G[0][a];
+        G[0][a] = gn[a];
+      }
     }
     jx1 = jxn;
     jy1 = jyn;
     tdp2 = tdp1;
     tdp1 = tdpn;
     irq = irn;
+  };
+
+  if constexpr (PD == 1) {
+    for (int it = 0; it < nit; ++it)
+      iteration(std::integral_constant<int, 0>{}, it);
+  } else {
+    // whole groups of three: iterations past nit issue no loads and their
+    // rows fall outside the B / C ranges, so they only cost arithmetic;
+    // without guards every path into a group has the same loads in flight,
+    // which keeps the compiler's wait counts exact
+    for (int it = 0; it < nit; it += 3) {
+      iteration(std::integral_constant<int, 0>{}, it);
+      iteration(std::integral_constant<int, 1>{}, it + 1);
+      iteration(std::integral_constant<int, 2>{}, it + 2);
+    }
   }
 }
 
