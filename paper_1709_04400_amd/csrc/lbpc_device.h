@@ -379,13 +379,15 @@ __device__ __forceinline__ void cook_g(const StepParams& p, const Shift<P>& sh,
 #pragma unroll
       for (int a = 1; a < Q; ++a) {
         const bool ox = e.ox(a), oy = e.oy(a), wall = e.wall(p, a);
-        // source column for the hot-spot test of the y- side
+        // source column for the hot-spot test of the y- side; temperatures
+        // selected in the compute type
         const int col = EXs[a] > 0 ? xm : (EXs[a] < 0 ? xp : x);
-        const double Ty =
-            EYs[a] > 0
-                ? (col >= p.hot_x0 && col < p.hot_x1 ? p.T_hot : p.T_bc[2])
-                : p.T_bc[3];
-        const C wT = C(w_rest(p, a) * (oy ? Ty : p.T_bc[EXs[a] > 0 ? 0 : 1]));
+        const C Ty = EYs[a] > 0 ? (col >= p.hot_x0 && col < p.hot_x1
+                                       ? C(p.T_hot)
+                                       : C(p.T_bc[2]))
+                                : C(p.T_bc[3]);
+        const C wT =
+            C(w_rest(p, a)) * (oy ? Ty : C(p.T_bc[EXs[a] > 0 ? 0 : 1]));
         g[a] = wall ? C(2) * wT - g[a] : ((ox || oy) ? wT : g[a]);
       }
     }

@@ -118,19 +118,32 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
   }
 
   // row r -> wrapped row, or -1 for a ghost row of a non-periodic y side
-  // Pulls are issued by every lane and every iteration, whether or not the
-  // row is used: lanes and rows without a node of their own read a clamped
-  // node, and the values are never used.  With no branch around the loads
-  // the compiler's wait counts follow only the loads actually in flight.
-  const int cl = cw < 0 ? 0 : (cw >= nx ? nx - 1 : cw);
-  auto pull_row = [&](int rw, typename Tr::R* fr, typename Tr::R* gr) {
-    pull_raw<P, GEN>(p, fin, gin, cl, rw < 0 ? Y0 : rw, fr, gr);
-  };
-
   auto wrap_row = [&](int r) -> int {
     if (r >= 0 && r < ny) return r;
     if (!p.pery) return -1;
     return r < 0 ? r + ny : r - ny;
+  };
+
+  // march direction alternates between vertically adjacent row runs, so the
+  // rows two runs share are pulled by both at the same time (both at their
+  // start or both at their end) and the second pull is served by L2
+  const int dir = (by & 1) ? -1 : 1;
+  const int nit = Y1 - Y0 + 4;
+  const int rfirst = dir > 0 ? Y0 - 2 : Y1 + 1;
+  const int rlast = rfirst + dir * (nit - 1);
+
+  // Pulls are issued by every lane and every iteration, whether or not the
+  // row is used: lanes without a node of their own read a clamped column,
+  // rows past the run read its last row and ghost rows the nearest lattice
+  // row (all recently read, so cache hits), and those values are never
+  // used.  With no branch around the loads the compiler's wait counts
+  // follow only the loads actually in flight.
+  const int cl = cw < 0 ? 0 : (cw >= nx ? nx - 1 : cw);
+  auto pull_row = [&](int rt, typename Tr::R* fr, typename Tr::R* gr) {
+    const int rc = dir > 0 ? min(rt, rlast) : max(rt, rlast);
+    int rw = wrap_row(rc);
+    if (rw < 0) rw = rc < 0 ? 0 : ny - 1;
+    pull_raw<P, GEN>(p, fin, gin, cl, rw, fr, gr);
   };
 
   // Pulled values stay as loaded (register images) until they are used, so
@@ -159,17 +172,8 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
   __shared__ C s_g[PD == 2 ? 3 : 1][PD == 2 ? Q : 1][PD == 2 ? BLOCK : 1];
   C jx1 = C(0), jy1 = C(0), tdp1 = C(0), tdp2 = C(0), irq = C(0);
 
-  // march direction alternates between vertically adjacent row runs, so the
-  // rows two runs share are pulled by both at the same time (both at their
-  // start or both at their end) and the second pull is served by L2
-  const int dir = (by & 1) ? -1 : 1;
-  const int nit = Y1 - Y0 + 4;
-  const int rfirst = dir > 0 ? Y0 - 2 : Y1 + 1;
 #pragma unroll
-  for (int k = 0; k < PD; ++k) {
-    const int rw = wrap_row(rfirst + k * dir);
-    pull_row(rw, F[k], G[k]);
-  }
+  for (int k = 0; k < PD; ++k) pull_row(rfirst + k * dir, F[k], G[k]);
 
   // one iteration; kc is the ring slot of row r (always 0 for PD = 1)
   auto iteration = [&](auto kc, const int it) __attribute__((always_inline)) {
@@ -341,12 +345,10 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
         fq1[a] = F[0][a];
         gn[a] = R(0);
       }
-      const int rwn = (it + 1 < nit) ? wrap_row(r + dir) : -1;
-      pull_row(rwn, F[0], gn);
+      pull_row(r + dir, F[0], gn);
     } else {
       // row r + 2 dir into the slot row r - 1 has just left
-      const int rwn = (it + 2 < nit) ? wrap_row(r + 2 * dir) : -1;
-      pull_row(rwn, F[kp], G[kp]);
+      pull_row(r + 2 * dir, F[kp], G[kp]);
     }
     __syncthreads();
 
@@ -390,11 +392,11 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
               if (ox) col = c;
               else if (col < 0) col += nx;
               else if (col >= nx) col -= nx;
-              const double Ty =
-                  ys == 2 ? (col >= p.hot_x0 && col < p.hot_x1 ? p.T_hot
-                                                                : p.T_bc[2])
-                          : p.T_bc[3];
-              const C Tg = C(oy ? Ty : p.T_bc[xs]);
+              const C Ty = ys == 2 ? (col >= p.hot_x0 && col < p.hot_x1
+                                          ? C(p.T_hot)
+                                          : C(p.T_bc[2]))
+                                   : C(p.T_bc[3]);
+              const C Tg = oy ? Ty : C(p.T_bc[xs]);
               Tn[k] = (ox || oy) ? Tg : Tn[k];
               vxn[k] = wall ? C(0) : vxn[k];
               vyn[k] = wall ? C(0) : vyn[k];
