@@ -144,22 +144,31 @@ typedef struct lbpc_diag {
 lbpc_status lbpc_workspace_bytes(const lbpc_config *cfg, size_t *bytes);
 
 /* Validates cfg and binds the workspace and stream (hipStream_t, may be
- * NULL for the null stream).  Nothing is launched.  On failure *out is NULL. */
+ * NULL for the null stream).  Nothing is launched; besides the handle the
+ * library allocates one 4-byte pinned host flag (host-mapped), which the
+ * step kernel sets on an invalid node state.  On failure *out is NULL. */
 lbpc_status lbpc_create(const lbpc_config *cfg, void *dev_workspace,
                         size_t workspace_bytes, void *hip_stream,
                         lbpc_handle **out);
 
 /* Initial fields: host FP64 arrays, row-major [ny][nx], copied (the call
- * returns after the copy).  Sets f = f^eq(rho, u), g = g^eq(T, u) (Eq. 53
- * moments mapped back by M^-1), rho_ave = mean rho, step = 0, and marks
- * phi_prev as unset (the first step uses phi_prev = phi).  Rejects rho <= 0,
- * rho >= 1/b, T <= 0, a negative psi^2 or non-finite values (LBPC_ERR_ARG). */
+ * returns after the copy).  Sets f = f^eq(rho, u), g = g^eq(T, u) (the
+ * equilibrium of the thermal model: Eq. 53 moments mapped back by M^-1, or
+ * Eq. 14 / Eq. 29 for the BGK models), rho_ave = mean rho, step = 0, marks
+ * phi_prev as unset (the first step uses phi_prev = phi) and clears the
+ * invalid-state flag.  Rejects rho <= 0, rho >= 1/b, T <= 0, a negative
+ * psi^2 or non-finite values (LBPC_ERR_ARG). */
 lbpc_status lbpc_init_fields(lbpc_handle *h, const double *rho,
                              const double *ux, const double *uy,
                              const double *T);
 
 /* Enqueues n >= 0 coupled time steps on the stream and returns without
- * waiting.  A non-finite state is reported by the next synchronising call. */
+ * waiting.  Each step checks every node's state (psi^2 >= 0, 0 < rho < 1/b,
+ * finite T, as the reference implementation does) and flags a violation.
+ * A flag set by a step that has completed makes lbpc_step return
+ * LBPC_ERR_NUMERIC without enqueuing; every synchronising call
+ * (lbpc_get_rho_u_T, lbpc_get_diag, lbpc_save_state) reports it exactly.
+ * lbpc_load_state (of a good state) and lbpc_init_fields clear it. */
 lbpc_status lbpc_step(lbpc_handle *h, int64_t n);
 
 /* Tile shape of the step launches: threads per block (64, 128 or 256; the
@@ -180,12 +189,15 @@ lbpc_status lbpc_autotune(lbpc_handle *h, int32_t steps, int32_t *block_width,
 lbpc_status lbpc_get_rho_u_T(lbpc_handle *h, double *rho, double *ux,
                              double *uy, double *T);
 
-/* Waits for the stream and fills *out. */
+/* Waits for the stream and fills *out; returns LBPC_ERR_NUMERIC (with *out
+ * filled and nonfinite = 1) when a step has flagged an invalid state. */
 lbpc_status lbpc_get_diag(lbpc_handle *h, lbpc_diag *out);
 
 /* Canonical state {f(t) [9][ny][nx], g(t) [9][ny][nx], phi(t-1) [ny][nx]}
- * as FP64, plus phi_valid, rho_ave and step: lbpc_state_bytes gives the
- * host buffer size; save waits for the stream. */
+ * as FP64 (for the BGK form of the improved model followed by T v_x and
+ * T v_y of step t-1, [ny][nx] each), then phi_valid, rho_ave and step as
+ * three 8-byte words: lbpc_state_bytes gives the host buffer size.  Save
+ * waits for the stream and refuses (LBPC_ERR_NUMERIC) a flagged state. */
 lbpc_status lbpc_state_bytes(const lbpc_handle *h, size_t *bytes);
 lbpc_status lbpc_save_state(lbpc_handle *h, void *host, size_t bytes);
 lbpc_status lbpc_load_state(lbpc_handle *h, const void *host, size_t bytes);

@@ -40,6 +40,10 @@ struct lbpc_handle {
   int table_fresh, table_phi_valid, table_valid, table_tuning;
   int nwork, grid;
   StepParams table_host[2];
+  // invalid-state flag written by the step kernel: host-mapped pinned
+  // memory, so lbpc_step can read it without waiting
+  int* bad_host;
+  int* bad_dev;
   std::string err;
 };
 
@@ -51,6 +55,38 @@ lbpc_status fail(lbpc_handle* h, lbpc_status st, const std::string& msg) {
   else
     g_err = msg;
   return st;
+}
+
+const char* const BAD_STATE =
+    "a step met an invalid node state (non-finite T, rho outside (0, 1/b) "
+    "or psi^2 < 0); load a saved state to continue";
+
+// flag of the invalid-state check (only meaningful once the launches that
+// may set it have completed)
+bool flagged(const lbpc_handle* h) {
+  return h->bad_host && *static_cast<volatile int*>(h->bad_host) != 0;
+}
+
+// the flag is allocated by the first call that touches the device (an
+// initialisation or a state load), and cleared there
+lbpc_status reset_flag(lbpc_handle* h) {
+  if (!h->bad_host) {
+    if (hipHostMalloc(reinterpret_cast<void**>(&h->bad_host), sizeof(int),
+                      hipHostMallocMapped) != hipSuccess) {
+      h->bad_host = nullptr;
+      return fail(h, LBPC_ERR_OOM, "pinned host flag allocation failed");
+    }
+    if (hipHostGetDevicePointer(reinterpret_cast<void**>(&h->bad_dev),
+                                h->bad_host, 0) != hipSuccess) {
+      (void)hipHostFree(h->bad_host);
+      h->bad_host = nullptr;
+      return fail(h, LBPC_ERR_HIP, "device address of the flag");
+    }
+    h->base.bad = h->bad_dev;
+    h->table_valid = 0;
+  }
+  *h->bad_host = 0;
+  return LBPC_OK;
 }
 
 lbpc_status hip_fail(lbpc_handle* h, hipError_t e, const char* what) {
@@ -234,6 +270,10 @@ lbpc_status lbpc_init_fields(lbpc_handle* h, const double* rho,
   StepParams p = params_now(h);
   HIP_TRY(h, lbpc::launch_init(p, c.precision, scr, h->stream), "init kernel");
   HIP_TRY(h, hipStreamSynchronize(h->stream), "init synchronise");
+  {
+    lbpc_status st = reset_flag(h);
+    if (st != LBPC_OK) return st;
+  }
   h->fresh = 1;
   h->phi_valid = 0;
   h->step = 0;
@@ -246,6 +286,8 @@ lbpc_status lbpc_step(lbpc_handle* h, int64_t n) {
   if (!h) return fail(nullptr, LBPC_ERR_ARG, "handle is NULL");
   if (n < 0) return fail(h, LBPC_ERR_ARG, "n < 0");
   if (!h->initialised) return fail(h, LBPC_ERR_STATE, "step before init");
+  // steps already completed may have flagged an invalid state
+  if (flagged(h)) return fail(h, LBPC_ERR_NUMERIC, BAD_STATE);
   for (int64_t s = 0; s < n; ++s) {
     lbpc_status st = enqueue_step(h, false);
     if (st != LBPC_OK) return st;
@@ -331,6 +373,7 @@ lbpc_status lbpc_get_rho_u_T(lbpc_handle* h, double* rho, double* ux,
                              hipMemcpyDeviceToHost, h->stream),
               "copy of the fields");
   HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+  if (flagged(h)) return fail(h, LBPC_ERR_NUMERIC, BAD_STATE);
   for (int k = 0; k < 4; ++k)
     if (dst[k])
       for (size_t i = 0; i < N; ++i)
@@ -367,8 +410,10 @@ lbpc_status lbpc_get_diag(lbpc_handle* h, lbpc_diag* out) {
   out->radius = std::sqrt(r[3] / M_PI);
   out->radius_count = std::sqrt(r[4] / M_PI);
   out->max_speed = r[5];
-  out->nonfinite = r[6] != 0.0 || !std::isfinite(r[0]) || !std::isfinite(r[1]);
+  out->nonfinite = r[6] != 0.0 || !std::isfinite(r[0]) ||
+                   !std::isfinite(r[1]) || flagged(h);
   out->step = h->step;
+  if (flagged(h)) return fail(h, LBPC_ERR_NUMERIC, BAD_STATE);
   return LBPC_OK;
 }
 
@@ -386,6 +431,8 @@ lbpc_status lbpc_save_state(lbpc_handle* h, void* host, size_t bytes) {
   size_t need;
   lbpc_state_bytes(h, &need);
   if (!host || bytes < need) return fail(h, LBPC_ERR_ARG, "buffer too small");
+  HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+  if (flagged(h)) return fail(h, LBPC_ERR_NUMERIC, BAD_STATE);
   const size_t N = (size_t)h->cfg.nx * h->cfg.ny;
   double* scr = static_cast<double*>(at(h, h->L.scratch));
   double* dst = static_cast<double*>(host);
@@ -455,6 +502,10 @@ lbpc_status lbpc_load_state(lbpc_handle* h, const void* host, size_t bytes) {
   h->phi_valid = meta[0] != 0;
   std::memcpy(&h->rho_ave, &meta[1], sizeof(double));
   h->step = meta[2];
+  {
+    lbpc_status st = reset_flag(h);
+    if (st != LBPC_OK) return st;
+  }
   h->fresh = 1;
   h->initialised = 1;
   h->table_fresh = -1;
@@ -464,6 +515,7 @@ lbpc_status lbpc_load_state(lbpc_handle* h, const void* host, size_t bytes) {
 void lbpc_destroy(lbpc_handle* h) {
   if (!h) return;
   if (h->initialised) (void)hipStreamSynchronize(h->stream);
+  if (h->bad_host) (void)hipHostFree(h->bad_host);
   delete h;
 }
 

@@ -118,6 +118,10 @@ struct lbpc_batch {
   int tuning;  // timing launches: state read in place, phi(t) to scratch
   hipGraphExec_t graph[2];
   int use_graph;
+  // per-lattice invalid-state flags written by the step kernel
+  // (host-mapped pinned memory, readable without waiting)
+  int* bad_host;
+  int* bad_dev;
   std::string err;
 };
 
@@ -141,6 +145,34 @@ lbpc_status bfail(lbpc_batch* b, lbpc_status st, const std::string& msg) {
 
 void* at(lbpc_batch* b, size_t off) { return b->ws + off; }
 
+const char* const BAD_STATE =
+    "a step met an invalid node state (non-finite T, rho outside (0, 1/b) "
+    "or psi^2 < 0) in this lattice";
+
+bool flagged(const lbpc_batch* b, int c) {
+  return b->bad_host && static_cast<volatile int*>(b->bad_host)[c] != 0;
+}
+
+// per-lattice flags, allocated by the first initialisation (the first call
+// that touches the device)
+lbpc_status ensure_flags(lbpc_batch* b) {
+  if (b->bad_host) return LBPC_OK;
+  if (hipHostMalloc(reinterpret_cast<void**>(&b->bad_host),
+                    (size_t)b->n * sizeof(int), hipHostMallocMapped) !=
+      hipSuccess) {
+    b->bad_host = nullptr;
+    return bfail(b, LBPC_ERR_OOM, "pinned host flag allocation failed");
+  }
+  for (int c = 0; c < b->n; ++c) b->bad_host[c] = 0;
+  if (hipHostGetDevicePointer(reinterpret_cast<void**>(&b->bad_dev),
+                              b->bad_host, 0) != hipSuccess) {
+    (void)hipHostFree(b->bad_host);
+    b->bad_host = nullptr;
+    return bfail(b, LBPC_ERR_HIP, "device address of the flags");
+  }
+  return LBPC_OK;
+}
+
 // parameters of lattice c when buffer `par` holds its state
 StepParams case_params(lbpc_batch* b, int c, int par) {
   StepParams p = b->base[c];
@@ -154,6 +186,7 @@ StepParams case_params(lbpc_batch* b, int c, int par) {
   p.fresh = b->fresh;
   p.phi_valid = b->phi_valid;
   p.rho_ave = b->rho_ave[c];
+  p.bad = b->bad_dev + c;
   p.bw = b->bw;
   p.W = b->bw - 2 * lbpc::HALO;
   p.H = b->rows;
@@ -260,6 +293,8 @@ lbpc_status lbpc_batch_create(const lbpc_config* cfgs, int32_t n,
   b->stream = static_cast<hipStream_t>(hip_stream);
   b->ws = static_cast<char*>(dev_workspace);
   b->L = L;
+  b->bad_host = nullptr;
+  b->bad_dev = nullptr;
   b->base.resize(n);
   for (int c = 0; c < n; ++c) derive_params(cfgs[c], b->base[c]);
   b->initialised.assign(n, 0);
@@ -295,6 +330,10 @@ lbpc_status lbpc_batch_init_fields(lbpc_batch* b, int32_t c,
     return bfail(b, LBPC_ERR_STATE, "initial fields after the first step");
   const char* bad = check_fields(b->cfgs[c], rho, ux, uy, T, &b->rho_ave[c]);
   if (bad) return bfail(b, LBPC_ERR_ARG, bad);
+  {
+    lbpc_status st = ensure_flags(b);
+    if (st != LBPC_OK) return st;
+  }
   const size_t N = (size_t)b->cfgs[c].nx * b->cfgs[c].ny;
   double* scr = static_cast<double*>(at(b, b->L.scratch));
   const double* src[4] = {rho, ux, uy, T};
@@ -306,6 +345,7 @@ lbpc_status lbpc_batch_init_fields(lbpc_batch* b, int32_t c,
   StepParams p = case_params(b, c, b->cur);
   BHIP(b, lbpc::launch_init(p, b->prec, scr, b->stream), "init kernel");
   BHIP(b, hipStreamSynchronize(b->stream), "synchronise");
+  b->bad_host[c] = 0;
   b->initialised[c] = 1;
   b->fresh = 1;
   b->phi_valid = 0;
@@ -387,6 +427,11 @@ lbpc_status lbpc_batch_step(lbpc_batch* b, int64_t n) {
   for (int c = 0; c < b->n; ++c)
     if (!b->initialised[c])
       return bfail(b, LBPC_ERR_STATE, "step before every lattice is set");
+  for (int c = 0; c < b->n; ++c)
+    if (flagged(b, c))
+      return bfail(b, LBPC_ERR_NUMERIC,
+                   std::string(BAD_STATE) + " (lattice " + std::to_string(c) +
+                       ")");
   while (n > 0) {
     const bool steady = !b->fresh && b->phi_valid;
     if (steady && (b->table_fresh || !b->table_phi_valid)) {
@@ -448,6 +493,7 @@ lbpc_status lbpc_batch_get_rho_u_T(lbpc_batch* b, int32_t c, double* rho,
                           hipMemcpyDeviceToHost, b->stream),
            "copy of the fields");
   BHIP(b, hipStreamSynchronize(b->stream), "synchronise");
+  if (flagged(b, c)) return bfail(b, LBPC_ERR_NUMERIC, BAD_STATE);
   for (int k = 0; k < 4; ++k)
     if (dst[k])
       for (size_t i = 0; i < N; ++i)
@@ -482,8 +528,10 @@ lbpc_status lbpc_batch_get_diag(lbpc_batch* b, int32_t c, lbpc_diag* out) {
   out->radius = std::sqrt(r[3] / M_PI);
   out->radius_count = std::sqrt(r[4] / M_PI);
   out->max_speed = r[5];
-  out->nonfinite = r[6] != 0.0 || !std::isfinite(r[0]) || !std::isfinite(r[1]);
+  out->nonfinite = r[6] != 0.0 || !std::isfinite(r[0]) ||
+                   !std::isfinite(r[1]) || flagged(b, c);
   out->step = b->step;
+  if (flagged(b, c)) return bfail(b, LBPC_ERR_NUMERIC, BAD_STATE);
   return LBPC_OK;
 }
 
@@ -499,6 +547,7 @@ void lbpc_batch_destroy(lbpc_batch* b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->stream);
   drop_graphs(b);
+  if (b->bad_host) (void)hipHostFree(b->bad_host);
   delete b;
 }
 

@@ -62,6 +62,8 @@ struct StepParams {
   void* phi_out;    // the same for step t; the same arrays except while
                     // the autotuner times steps
   long long N;      // nx * ny
+  int* bad;         // set to 1 when a step meets an invalid node state
+                    // (host-mapped memory, read by the host without waiting)
 };
 
 // ------------------------------------------------------- precision traits

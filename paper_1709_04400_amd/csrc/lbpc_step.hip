@@ -209,7 +209,9 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
       //   T dp/dT = (rho R T D2 + a kappa s sqrt(T/Tc) rho^2 D1) / (D1 D2),
       // D1 = 1 - b rho, D2 = 1 + 2 b rho - b^2 rho^2, s = 1 + kappa (1 -
       // sqrt(T/Tc)), th = s^2 (using T dth/dT = -kappa s sqrt(T/Tc))
+      // the state a node may hold: psi^2 >= 0, 0 < rho < 1/b, finite T
       double psi;
+      bool valid;
       if constexpr (sizeof(C) == 8) {
         const double rd = rho, Td = T;
         const double sq = sqrt(Td * p.inv_Tc);
@@ -223,6 +225,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
         const double psi2 = p.two_over_G * (pe - rd * (1.0 / 3.0));
         psi = sqrt(psi2 > 0.0 ? psi2 : 0.0);
         tdpn = C((rRT + ar2 * p.kappa * s * sq) * inv);
+        valid = psi2 >= 0.0 && rd > 0.0 && brho < 1.0 && Td - Td == 0.0;
       } else {
         // FP32 arithmetic: the smooth factors (sqrt(T/Tc), s, 1/(D1 D2))
         // in FP32, the cancelling combinations (repulsive - attractive
@@ -240,7 +243,9 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
         const double psi2 = p.two_over_G * (pe - rd * (1.0 / 3.0));
         psi = sqrtf(float(psi2 > 0.0 ? psi2 : 0.0));
         tdpn = C((rRT + ar2 * (p.kappa * (double)(s * sq))) * (double)inv);
+        valid = psi2 >= 0.0 && rd > 0.0 && rd * p.b < 1.0 && T - T == 0.0f;
       }
+      if (!valid) *p.bad = 1;
       s_rho[sl0][t] = rho;
       s_T[sl0][t] = T;
       s_psi[sl0][t] = C(psi);

@@ -1,0 +1,175 @@
+"""Failure detection, recovery and determinism through the C ABI.
+
+The step kernel flags a node whose state is invalid by the oracle's own
+criteria (psi^2 < 0, rho outside (0, 1/b), non-finite T); the flag lives in
+host-mapped memory, so lbpc_step reports it (LBPC_ERR_NUMERIC) without
+waiting and every synchronising call reports it exactly.  Conditions are
+forced from the host: a state with a planted NaN or an impossible density is
+loaded through lbpc_load_state, or a lattice is started in a flow the scheme
+cannot carry.  Recovery is a load of a saved state, after which the run must
+be bitwise the uninterrupted one.  The determinism tests run every kernel
+form twice and require bitwise equal results (an LDS race or a missing
+barrier would break them).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1709_04400_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+NUMERIC = -5
+
+
+def _lb():
+    from paper_1709_04400_amd import lbpc
+    return lbpc
+
+
+def _sim(cfg, fl):
+    g = _lb().Simulation(cfg)
+    g.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
+    return g
+
+
+def _status(fn):
+    try:
+        fn()
+    except _lb().LbpcError as e:
+        return e.status
+    return 0
+
+
+def test_planted_nan_is_reported_and_a_reload_recovers_exactly():
+    cfg, fl = I.static_droplet(48, 40, 12.0)
+    cfg["gy"] = -2e-5
+    g = _sim(cfg, fl)
+    g.step(20)
+    good = g.save_state()
+    g.step(30)
+    ref = g.rho_u_T()
+    g.close()
+
+    n = 48 * 40
+    bad = good.copy()                         # bytes: view as FP64 words
+    bad.view(np.float64)[5 * n + 17 * 48 + 30] = np.nan   # f_5 at (30, 17)
+    h = _lb().Simulation(cfg)
+    h.load_state(bad)
+    h.step(3)                                 # enqueued: nothing seen yet
+    assert _status(h.diag) == NUMERIC         # synchronising call reports it
+    assert _status(lambda: h.step(1)) == NUMERIC   # so does the next step
+    assert _status(h.save_state) == NUMERIC
+    h.load_state(good)                        # recovery
+    h.step(30)
+    for a, b in zip(ref, h.rho_u_T()):
+        assert np.array_equal(a, b)
+    h.close()
+
+
+def test_impossible_density_is_flagged_like_the_oracle():
+    """rho >= 1/b at one node: the oracle's step fails on it, and so does the
+    GPU step, with the same status."""
+    cfg, fl = I.static_droplet(40, 40, 10.0)
+    g = _sim(cfg, fl)
+    g.step(5)
+    st = g.save_state()
+    g.close()
+    n = 40 * 40
+    st2 = st.copy()
+    w = st2.view(np.float64)                  # the state as FP64 words
+    f = w[:9 * n].reshape(9, 40, 40)
+    f[0, 20, 20] += 12.0                      # rho = 6.5 + 12 > 1/b = 10.5
+    meta = w[19 * n:].view(np.int64)
+    o = O.Oracle(cfg)
+    o.set_state({"f": f.copy(), "g": w[9 * n:18 * n].reshape(9, 40, 40),
+                 "phi_prev": w[18 * n:19 * n].reshape(40, 40),
+                 "phi_valid": int(meta[0]), "rho_ave": float(w[19 * n + 1]),
+                 "step": int(meta[2])})
+    with pytest.raises(O.OracleError) as e:
+        o.step(1)
+    assert e.value.status == NUMERIC
+    h = _lb().Simulation(cfg)
+    h.load_state(st2)
+    h.step(1)
+    assert _status(h.diag) == NUMERIC
+    h.close()
+
+
+def test_runaway_flow_fails_on_the_same_step_as_the_oracle():
+    """A droplet in a uniform flow u = 0.5 leaves the scheme's range: the
+    first step that meets an invalid state is the same on both sides."""
+    cfg, fl = I.static_droplet(32, 32, 8.0)
+    fl["ux"] = np.full((32, 32), 0.5)
+    o = O.Oracle(cfg)
+    o.init_fields(**fl)
+    o_fail = None
+    for s in range(1, 60):
+        try:
+            o.step(1)
+        except O.OracleError:
+            o_fail = s
+            break
+    assert o_fail is not None
+    g = _sim(cfg, fl)
+    g_fail = None
+    for s in range(1, 60):
+        g.step(1)
+        if _status(g.diag) == NUMERIC:
+            g_fail = s
+            break
+    g.close()
+    assert g_fail == o_fail, (g_fail, o_fail)
+
+
+def test_batch_flags_only_the_failing_lattice():
+    good_c, good_f = I.heated_droplet(48, 10.0, 1.1)
+    bad_c, bad_f = I.static_droplet(32, 32, 8.0)
+    bad_f["ux"] = np.full((32, 32), 0.5)
+    b = _lb().Batch([good_c, bad_c])
+    b.init_fields(0, good_f["rho"], good_f["ux"], good_f["uy"], good_f["T"])
+    b.init_fields(1, bad_f["rho"], bad_f["ux"], bad_f["uy"], bad_f["T"])
+    b.step(60)
+    assert _status(lambda: b.diag(1)) == NUMERIC
+    assert not b.diag(0)["nonfinite"]
+    assert _status(lambda: b.step(1)) == NUMERIC
+    b.close()
+
+
+# ----------------------------------------------------------- determinism --
+
+def _twice(cfg, fl, steps):
+    out = []
+    for _ in range(2):
+        g = _sim(cfg, fl)
+        g.step(steps)
+        out.append(g.rho_u_T())
+        g.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", [I.FP64, I.FP32, I.FP32_SHIFTED,
+                                  I.FP16_SHIFTED])
+@pytest.mark.parametrize("sides", ["periodic", "walls"])
+def test_run_twice_is_bitwise_identical(prec, sides):
+    cfg, fl = I.bubble(nx=300, ny=96, pool=60, hot_width=20, g=3e-5,
+                       precision=prec)
+    if sides == "periodic":
+        cfg["bc"] = [I.BC_PERIODIC] * 4
+    a, b = _twice(cfg, fl, 120)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_batch_run_twice_is_bitwise_identical():
+    cases = I.batch_cases(count=12, seed=3, precision=I.FP16_SHIFTED)
+    res = []
+    for _ in range(2):
+        b = _lb().Batch([c for c, _ in cases])
+        for k, (_, f) in enumerate(cases):
+            b.init_fields(k, f["rho"], f["ux"], f["uy"], f["T"])
+        b.step(41)
+        res.append([b.rho_u_T(k) for k in range(len(cases))])
+        b.close()
+    for ra, rb in zip(*res):
+        for x, y in zip(ra, rb):
+            assert np.array_equal(x, y)
