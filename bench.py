@@ -69,7 +69,7 @@ def gpu_run(n, prec, steps, warmup, per_launch=40, model=0):
 def batch_run(count, steps, warmup):
     """The batched sweep: `count` heated-wall droplets of sizes drawn from
     {64, 96, ..., 512}, FP32 storage, one persistent launch per step,
-    graph-replayed steps, autotuned tiles."""
+    autotuned tiles."""
     import torch
     from paper_1709_04400_amd import inputs, lbpc
     cases = inputs.batch_cases(count=count, seed=1709,

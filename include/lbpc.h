@@ -163,7 +163,10 @@ lbpc_status lbpc_init_fields(lbpc_handle *h, const double *rho,
                              const double *T);
 
 /* Enqueues n >= 0 coupled time steps on the stream and returns without
- * waiting.  Each step checks every node's state (psi^2 >= 0, 0 < rho < 1/b,
+ * waiting.  With LBPC_GRAPH=1 in the environment at lbpc_create and a
+ * non-NULL stream, steady-state pairs of steps are replayed from a captured
+ * hipGraph of one ping-pong period (same results; on MI355X eager launches
+ * measured slightly faster, so it is off by default).  Each step checks every node's state (psi^2 >= 0, 0 < rho < 1/b,
  * finite T, as the reference implementation does) and flags a violation.
  * A flag set by a step that has completed makes lbpc_step return
  * LBPC_ERR_NUMERIC without enqueuing; every synchronising call
@@ -215,8 +218,10 @@ const char *lbpc_last_error(const lbpc_handle *h);
  * storage precision) advanced together: one persistent kernel launch per
  * time step walks a list of (lattice, tile) work items, costliest first.
  * Every lattice computes exactly what a single handle with its
- * configuration computes.  With a non-NULL stream, steady-state steps are
- * replayed from a captured hipGraph of two steps (one ping-pong period). */
+ * configuration computes.  With LBPC_BATCH_GRAPH=1 in the environment at
+ * creation and a non-NULL stream, steady-state steps are replayed from a
+ * captured hipGraph of two steps (one ping-pong period); off by default
+ * (eager launches measured slightly faster). */
 typedef struct lbpc_batch lbpc_batch;
 
 /* Device bytes for the batch (all lattices, the work list, shared scratch). */

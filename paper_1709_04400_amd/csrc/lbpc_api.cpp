@@ -44,6 +44,10 @@ struct lbpc_handle {
   // memory, so lbpc_step can read it without waiting
   int* bad_host;
   int* bad_dev;
+  // steady-state steps are replayed from a captured graph of one ping-pong
+  // period (two launches), one per starting buffer
+  hipGraphExec_t graph[2];
+  int use_graph;
   std::string err;
 };
 
@@ -117,9 +121,18 @@ StepParams params_now(lbpc_handle* h) {
   return p;
 }
 
+void drop_graphs(lbpc_handle* h) {
+  for (int k = 0; k < 2; ++k)
+    if (h->graph[k]) {
+      (void)hipGraphExecDestroy(h->graph[k]);
+      h->graph[k] = nullptr;
+    }
+}
+
 // tile shape of the step launches; the tile list of the non-periodic path
 // is rebuilt (and re-uploaded) at the next launch
 void set_tiles_impl(lbpc_handle* h, int bw, int rows) {
+  drop_graphs(h);
   StepParams& p = h->base;
   p.bw = bw;
   p.W = bw - 2 * lbpc::HALO;
@@ -133,16 +146,10 @@ void set_tiles_impl(lbpc_handle* h, int bw, int rows) {
   }
 }
 
-// one launch of the step on the current state (buffer cur -> 1 - cur); the
-// caller flips the state afterwards, except for the autotuner, whose timing
-// launches send phi(t) to scratch and leave the state as it is
-lbpc_status enqueue_step(lbpc_handle* h, bool tuning) {
-  StepParams p = params_now(h);
-  if (tuning) p.phi_out = at(h, h->L.tune_phi);
-  if (!h->tiled)
-    return lbpc::launch_step(p, h->cfg.precision, h->stream) == hipSuccess
-               ? LBPC_OK
-               : fail(h, LBPC_ERR_HIP, "step kernel launch");
+// uploads the non-periodic path needs before its launches (tile list,
+// parameter table for the current state flags); none when they are current
+lbpc_status prepare_step(lbpc_handle* h, bool tuning) {
+  if (!h->tiled) return LBPC_OK;
   if (!h->table_valid) {
     const StepParams& b = h->base;
     std::vector<std::array<int, 4>> tiles;
@@ -178,6 +185,17 @@ lbpc_status enqueue_step(lbpc_handle* h, bool tuning) {
     h->table_phi_valid = h->phi_valid;
     h->table_tuning = want_tune;
   }
+  return LBPC_OK;
+}
+
+// the launch alone (capturable: no uploads, no waits)
+lbpc_status launch_now(lbpc_handle* h, bool tuning) {
+  StepParams p = params_now(h);
+  if (tuning) p.phi_out = at(h, h->L.tune_phi);
+  if (!h->tiled)
+    return lbpc::launch_step(p, h->cfg.precision, h->stream) == hipSuccess
+               ? LBPC_OK
+               : fail(h, LBPC_ERR_HIP, "step kernel launch");
   HIP_TRY(h,
           lbpc::launch_step_batch(
               static_cast<const StepParams*>(at(h, h->L.table)),
@@ -186,6 +204,14 @@ lbpc_status enqueue_step(lbpc_handle* h, bool tuning) {
               !(p.perx && p.pery) || env_int("LBPC_FORCE_GEN", 0)),
           "step kernel");
   return LBPC_OK;
+}
+
+// one launch of the step on the current state (buffer cur -> 1 - cur); the
+// caller flips the state afterwards, except for the autotuner, whose timing
+// launches send phi(t) to scratch and leave the state as it is
+lbpc_status enqueue_step(lbpc_handle* h, bool tuning) {
+  lbpc_status st = prepare_step(h, tuning);
+  return st == LBPC_OK ? launch_now(h, tuning) : st;
 }
 
 }  // namespace
@@ -242,6 +268,9 @@ lbpc_status lbpc_create(const lbpc_config* cfg, void* dev_workspace,
       if (rows > 256) rows = 256;
     }
     p.xcd_order = env_int("LBPC_XCD_ORDER", 1);
+    // graph replay (on request: eager launches measured faster here) needs
+    // a capturable (non-NULL) stream
+    h->use_graph = h->stream != nullptr && env_int("LBPC_GRAPH", 0) != 0;
     h->tiled = !(p.perx && p.pery) || env_int("LBPC_FORCE_TILED", 0);
     set_tiles_impl(h, bw, rows);
   }
@@ -268,6 +297,7 @@ lbpc_status lbpc_init_fields(lbpc_handle* h, const double* rho,
             "copy of the initial fields");
   h->cur = 0;
   StepParams p = params_now(h);
+  drop_graphs(h);
   HIP_TRY(h, lbpc::launch_init(p, c.precision, scr, h->stream), "init kernel");
   HIP_TRY(h, hipStreamSynchronize(h->stream), "init synchronise");
   {
@@ -288,13 +318,45 @@ lbpc_status lbpc_step(lbpc_handle* h, int64_t n) {
   if (!h->initialised) return fail(h, LBPC_ERR_STATE, "step before init");
   // steps already completed may have flagged an invalid state
   if (flagged(h)) return fail(h, LBPC_ERR_NUMERIC, BAD_STATE);
-  for (int64_t s = 0; s < n; ++s) {
+  while (n > 0) {
+    // steady state (state flags fixed): pairs of steps replay the graph of
+    // one ping-pong period that starts from the current buffer
+    if (h->use_graph && !h->fresh && h->phi_valid && n >= 2) {
+      lbpc_status st = prepare_step(h, false);
+      if (st != LBPC_OK) return st;
+      hipGraphExec_t& g = h->graph[h->cur];
+      if (!g) {
+        hipGraph_t graph;
+        HIP_TRY(h,
+                hipStreamBeginCapture(h->stream,
+                                      hipStreamCaptureModeThreadLocal),
+                "graph capture");
+        const int keep = h->cur;
+        st = launch_now(h, false);
+        h->cur = 1 - keep;
+        lbpc_status st2 = st == LBPC_OK ? launch_now(h, false) : st;
+        h->cur = keep;
+        hipError_t e = hipStreamEndCapture(h->stream, &graph);
+        if (st2 != LBPC_OK) return st2;
+        HIP_TRY(h, e, "graph capture");
+        HIP_TRY(h, hipGraphInstantiate(&g, graph, nullptr, nullptr, 0),
+                "graph instantiate");
+        (void)hipGraphDestroy(graph);
+      }
+      const int64_t pairs = n / 2;
+      for (int64_t k = 0; k < pairs; ++k)
+        HIP_TRY(h, hipGraphLaunch(g, h->stream), "graph launch");
+      h->step += 2 * pairs;
+      n -= 2 * pairs;
+      continue;
+    }
     lbpc_status st = enqueue_step(h, false);
     if (st != LBPC_OK) return st;
     h->cur = 1 - h->cur;
     h->fresh = 0;
     h->phi_valid = 1;
     h->step += 1;
+    n -= 1;
   }
   return LBPC_OK;
 }
@@ -474,6 +536,7 @@ lbpc_status lbpc_load_state(lbpc_handle* h, const void* host, size_t bytes) {
   const size_t N = (size_t)h->cfg.nx * h->cfg.ny;
   double* scr = static_cast<double*>(at(h, h->L.scratch));
   const double* src = static_cast<const double*>(host);
+  drop_graphs(h);
   h->cur = 0;
   StepParams p = params_now(h);
   for (int which = 0; which < 18; ++which) {
@@ -515,6 +578,7 @@ lbpc_status lbpc_load_state(lbpc_handle* h, const void* host, size_t bytes) {
 void lbpc_destroy(lbpc_handle* h) {
   if (!h) return;
   if (h->initialised) (void)hipStreamSynchronize(h->stream);
+  drop_graphs(h);
   if (h->bad_host) (void)hipHostFree(h->bad_host);
   delete h;
 }

@@ -307,8 +307,9 @@ lbpc_status lbpc_batch_create(const lbpc_config* cfgs, int32_t n,
   if (b->bw != 64 && b->bw != 128 && b->bw != 256) b->bw = 256;
   b->rows = std::max(MIN_ROWS, env_int("LBPC_TILE_H", 32));
   b->graph[0] = b->graph[1] = nullptr;
-  // graph replay needs a capturable (non-NULL) stream
-  b->use_graph = b->stream != nullptr && env_int("LBPC_BATCH_GRAPH", 1) != 0;
+  // graph replay (on request: eager launches measured faster here) needs a
+  // capturable (non-NULL) stream
+  b->use_graph = b->stream != nullptr && env_int("LBPC_BATCH_GRAPH", 0) != 0;
   lbpc_status st = build_work(b);
   if (st != LBPC_OK) {
     g_berr = b->err;

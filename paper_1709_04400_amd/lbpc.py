@@ -215,7 +215,10 @@ def lbpc_destroy(h):
 # ------------------------------------------------------------- wrapper ---
 
 class Simulation:
-    """One lattice on one GPU: workspace from torch, library handle."""
+    """One lattice on one GPU: workspace from torch, library handle.
+
+    Uses its own (default-priority) torch stream unless one is given (a
+    capturable stream, for the optional hipGraph replay of steady steps)."""
 
     def __init__(self, cfg: dict, device: str = "cuda:0", stream=None):
         import torch
@@ -230,7 +233,7 @@ class Simulation:
         ptr = self.ws.data_ptr()
         ptr = (ptr + 255) // 256 * 256
         self.stream = stream if stream is not None else \
-            torch.cuda.current_stream(self.device)
+            torch.cuda.Stream(self.device)
         self.h = lbpc_create(cfg, ptr, nbytes, self.stream.cuda_stream)
 
     def init_fields(self, rho, ux, uy, T):
@@ -302,8 +305,8 @@ def lbpc_batch_workspace_bytes(cfgs) -> int:
 class Batch:
     """Many independent lattices stepped by one persistent launch per step.
 
-    Uses its own (default-priority) torch stream, so that steady-state steps
-    are replayed from a captured hipGraph."""
+    Uses its own (default-priority) torch stream (a capturable stream, for
+    the optional hipGraph replay of steady steps)."""
 
     def __init__(self, cfgs, device: str = "cuda:0", stream=None):
         import torch
