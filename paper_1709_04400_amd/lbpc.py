@@ -8,6 +8,7 @@ handle with its workspace.  Loading fails loudly when the library is absent.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 
 import numpy as np
@@ -214,6 +215,20 @@ def lbpc_destroy(h):
 
 # ------------------------------------------------------------- wrapper ---
 
+def _log_records(log, records):
+    """Appends records as JSON lines to `log` (a path or a text file)."""
+    if log is None:
+        return
+    if isinstance(log, (str, os.PathLike)):
+        with open(log, "a") as fh:
+            for r in records:
+                fh.write(json.dumps(r) + "\n")
+    else:
+        for r in records:
+            log.write(json.dumps(r) + "\n")
+        log.flush()
+
+
 class Simulation:
     """One lattice on one GPU: workspace from torch, library handle.
 
@@ -260,6 +275,20 @@ class Simulation:
 
     def diag(self) -> dict:
         return lbpc_get_diag(self.h)
+
+    def run(self, steps: int, every: int, log=None) -> list:
+        """Advances `steps` steps, taking the FP64 diagnostics after every
+        `every` steps (and after the last); returns the records and appends
+        each as one JSON line to `log` (a path or text file) if given."""
+        out = []
+        done = 0
+        while done < steps:
+            k = min(every, steps - done)
+            self.step(k)
+            done += k
+            out.append(self.diag())
+        _log_records(log, out)
+        return out
 
     def save_state(self) -> np.ndarray:
         return lbpc_save_state(self.h)
@@ -366,6 +395,22 @@ class Batch:
         _bcheck(lib().lbpc_batch_get_diag(self.h, int(c), ctypes.byref(d)),
                 self.h)
         return {n: getattr(d, n) for n, _ in Diag._fields_ if n != "pad"}
+
+    def run(self, steps: int, every: int, log=None) -> list:
+        """Advances every lattice `steps` steps, taking each lattice's FP64
+        diagnostics after every `every` steps (and after the last); returns
+        the records (each with its lattice index) and appends them as JSON
+        lines to `log` if given."""
+        out = []
+        done = 0
+        while done < steps:
+            k = min(every, steps - done)
+            self.step(k)
+            done += k
+            for c in range(len(self.cfgs)):
+                out.append(dict(self.diag(c), lattice=c))
+        _log_records(log, out)
+        return out
 
     def nodes(self) -> int:
         v = ctypes.c_int64()

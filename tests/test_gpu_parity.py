@@ -219,3 +219,32 @@ def test_graph_replay_equals_eager(monkeypatch, which):
         assert np.array_equal(x, y)
     for g in sims:
         g.close()
+
+
+def test_diagnostics_log(tmp_path):
+    """run(): diagnostics every K steps as records and JSON lines; mass is
+    conserved on a periodic lattice and sum T follows the oracle."""
+    import json
+    cfg, fl = I.static_droplet(64, 48, 12.0)
+    g = _gpu().Simulation(cfg)
+    g.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
+    m0 = g.diag()["mass"]
+    path = tmp_path / "diag.jsonl"
+    recs = g.run(100, 30, log=str(path))
+    g.close()
+    assert [r["step"] for r in recs] == [30, 60, 90, 100]
+    lines = [json.loads(x) for x in path.read_text().splitlines()]
+    assert lines == recs
+    assert max(abs(r["mass"] - m0) / m0 for r in recs) < 1e-12
+    o = O.Oracle(cfg)
+    o.init_fields(**fl)
+    o.step(100)
+    assert np.isclose(recs[-1]["sum_T"], o.diag()["sum_T"], rtol=1e-12)
+    b = _gpu().Batch([cfg, I.heated_droplet(40, 8.0, 1.1)[0]])
+    b.init_fields(0, fl["rho"], fl["ux"], fl["uy"], fl["T"])
+    f1 = I.heated_droplet(40, 8.0, 1.1)[1]
+    b.init_fields(1, f1["rho"], f1["ux"], f1["uy"], f1["T"])
+    brec = b.run(50, 25)
+    b.close()
+    assert [(r["lattice"], r["step"]) for r in brec] == \
+        [(0, 25), (1, 25), (0, 50), (1, 50)]
