@@ -22,6 +22,8 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_init(StepParams p,
   if (i >= N) return;
   const double rho = in[i], vx = in[N + i], vy = in[2 * N + i],
                T = in[3 * N + i];
+  const long long y = i / p.nx;
+  const int x = (int)(i - y * p.nx);
   const double v2 = vx * vx + vy * vy;
   double m[Q], f[Q];
   m[0] = rho;
@@ -38,7 +40,7 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_init(StepParams p,
   S* go = static_cast<S*>(const_cast<void*>(p.gin));
 #pragma unroll
   for (int a = 0; a < Q; ++a)
-    Tr::st(fo, a * N + i,
+    Tr::st(fo, dix(p.nx, a, y, x),
            typename Tr::C(f[a] - (Tr::shift ? w_lat(a) * p.rho_ref : 0.0)));
   if (p.gc) {
 #pragma unroll
@@ -65,7 +67,7 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_init(StepParams p,
   }
 #pragma unroll
   for (int a = 0; a < Q; ++a)
-    Tr::st(go, a * N + i,
+    Tr::st(go, dix(p.nx, a, y, x),
            typename Tr::C(f[a] - (Tr::shift ? w_rest(p, a) * p.T_ref : 0.0)));
 }
 
@@ -210,13 +212,15 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_load(StepParams p, int which,
   const long long i = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
   if (i >= N) return;
   const int a = which % Q;
+  const long long y = i / p.nx;
+  const long long o = dix(p.nx, a, y, (int)(i - y * p.nx));
   if (which < Q) {
     S* fo = static_cast<S*>(const_cast<void*>(p.fin));
-    Tr::st(fo, a * N + i,
+    Tr::st(fo, o,
            typename Tr::C(in[i] - (Tr::shift ? w_lat(a) * p.rho_ref : 0.0)));
   } else {
     S* go = static_cast<S*>(const_cast<void*>(p.gin));
-    Tr::st(go, a * N + i,
+    Tr::st(go, o,
            typename Tr::C(in[i] - (Tr::shift ? w_rest(p, a) * p.T_ref : 0.0)));
   }
 }

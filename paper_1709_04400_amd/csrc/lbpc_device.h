@@ -268,6 +268,15 @@ struct Shift {
 //   cook_g    then applies the value rules of g at edge nodes (again only
 //             in waves that hold one).
 
+// Distribution buffers interleave the rows of the nine direction arrays,
+// [ny][9][nx]: value a of node (x, y) is element dix(nx, a, y, x).  A tile
+// row then reads and writes one contiguous stretch of each buffer (plus the
+// neighbour rows of the pull) instead of nine arrays a lattice apart, which
+// the HBM serves faster than the same bytes spread over 18 streams.
+__device__ __forceinline__ long long dix(int nx, int a, long long y, int x) {
+  return (y * Q + a) * nx + x;
+}
+
 constexpr int EXs[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 constexpr int EYs[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 constexpr int OPs[Q] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
@@ -311,32 +320,28 @@ __device__ __forceinline__ void pull_raw(
     typename Prec<P>::R fr[Q], typename Prec<P>::R gr[Q]) {
   using Tr = Prec<P>;
   const int nx = p.nx, ny = p.ny;
-  const long long N = p.N;
-  const long long self = (long long)y * nx + x;
   // element offset of each direction's source; one set of loads serves
   // every case below, so the loads never sit in divergent branches
   long long off[Q];
   if (p.fresh) {
 #pragma unroll
-    for (int a = 0; a < Q; ++a) off[a] = a * N + self;
+    for (int a = 0; a < Q; ++a) off[a] = dix(nx, a, y, x);
   } else {
     const int xm = wrap_or_clamp(x - 1, nx, !GEN || p.perx);
     const int xp = wrap_or_clamp(x + 1, nx, !GEN || p.perx);
     const int ym = wrap_or_clamp(y - 1, ny, !GEN || p.pery);
     const int yp = wrap_or_clamp(y + 1, ny, !GEN || p.pery);
-    const long long row = (long long)y * nx;
-    const long long rm = (long long)ym * nx, rp = (long long)yp * nx;
     // source of direction a is x - e_a
-    const long long src[Q] = {row + x,  row + xm, rm + x,  row + xp, rp + x,
-                              rm + xm, rm + xp,  rp + xp, rp + xm};
+    const int ys[Q] = {y, y, ym, y, yp, ym, ym, yp, yp};
+    const int xs[Q] = {x, xm, x, xp, x, xm, xp, xp, xm};
 #pragma unroll
-    for (int a = 0; a < Q; ++a) off[a] = a * N + src[a];
+    for (int a = 0; a < Q; ++a) off[a] = dix(nx, a, ys[a], xs[a]);
     if (GEN) {
       const EdgeSides e(p, x, y, true);
       if (__builtin_amdgcn_ballot_w64(e.any()) != 0) {
 #pragma unroll
         for (int a = 1; a < Q; ++a)
-          if (e.wall(p, a)) off[a] = OPs[a] * N + self;
+          if (e.wall(p, a)) off[a] = dix(nx, OPs[a], y, x);
       }
     }
   }

@@ -319,9 +319,9 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
             ms[k] = m[k] - sf[k] * (m[k] - meq[k]) +
                     (C(1) - C(0.5) * sf[k]) * Sf[k];
           from_moments(ms, fo);
-          const long long o = (long long)rb * nx + c;
 #pragma unroll
-          for (int a = 0; a < Q; ++a) Tr::st(fout, a * N + o, fo[a] - sh.f(a));
+          for (int a = 0; a < Q; ++a)
+            Tr::st(fout, dix(nx, a, rb, c), fo[a] - sh.f(a));
         }
       }
     }
@@ -512,7 +512,8 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
           from_moments(ns, go);
         }
 #pragma unroll
-        for (int a = 0; a < Q; ++a) Tr::st(gout, a * N + o, go[a] - sh.g(a));
+        for (int a = 0; a < Q; ++a)
+          Tr::st(gout, dix(nx, a, yc, c), go[a] - sh.g(a));
       }
     }
 
