@@ -229,7 +229,8 @@ def copy_calibration(mib):
 
 def read_traffic(path, n):
     """HBM bytes per step launch from the committed counter summary, used
-    only while the kernel source is the one the counters were taken on."""
+    only while the kernel source and the host code that picks its tile
+    shape are the ones the counters were taken on."""
     if not os.path.exists(path):
         return None
     vals = {}
@@ -250,7 +251,8 @@ def read_traffic(path, n):
 def _kernel_hash():
     import hashlib
     h = hashlib.sha256()
-    for name in ("lbpc_step.hip", "lbpc_device.h"):
+    for name in ("lbpc_step.hip", "lbpc_device.h", "lbpc_host.h",
+                 "lbpc_api.cpp"):
         with open(os.path.join(ROOT, "paper_1709_04400_amd", "csrc",
                                name), "rb") as f:
             h.update(f.read())

@@ -135,8 +135,7 @@ void set_tiles_impl(lbpc_handle* h, int bw, int rows) {
   drop_graphs(h);
   StepParams& p = h->base;
   p.bw = bw;
-  p.W = bw - 2 * lbpc::HALO;
-  p.nbx = (h->cfg.nx + p.W - 1) / p.W;
+  strip_shape(h->cfg.nx, bw, h->cfg.precision == LBPC_FP64, p.nbx, p.W);
   p.H = rows;
   p.nby = (h->cfg.ny + p.H - 1) / p.H;
   if (h->tiled) {

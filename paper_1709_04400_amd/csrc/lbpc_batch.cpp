@@ -188,9 +188,8 @@ StepParams case_params(lbpc_batch* b, int c, int par) {
   p.rho_ave = b->rho_ave[c];
   p.bad = b->bad_dev + c;
   p.bw = b->bw;
-  p.W = b->bw - 2 * lbpc::HALO;
+  strip_shape(p.nx, b->bw, true, p.nbx, p.W);
   p.H = b->rows;
-  p.nbx = (p.nx + p.W - 1) / p.W;
   p.nby = (p.ny + p.H - 1) / p.H;
   p.xcd_order = 0;
   return p;
@@ -222,7 +221,6 @@ void drop_graphs(lbpc_batch* b) {
 
 // work list for the current tile shape: tiles of the largest lattices first
 lbpc_status build_work(lbpc_batch* b) {
-  const int W = b->bw - 2 * lbpc::HALO;
   std::vector<int> order(b->n);
   for (int c = 0; c < b->n; ++c) order[c] = c;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
@@ -231,7 +229,8 @@ lbpc_status build_work(lbpc_batch* b) {
   });
   std::vector<WorkItem> tiles;
   for (int c : order) {
-    const int nbx = (b->cfgs[c].nx + W - 1) / W;
+    int nbx, W;
+    strip_shape(b->cfgs[c].nx, b->bw, true, nbx, W);
     const int nby = (b->cfgs[c].ny + b->rows - 1) / b->rows;
     for (int by = 0; by < nby; ++by)
       for (int bx = 0; bx < nbx; ++bx) tiles.push_back({c, bx, by, 0});
