@@ -95,7 +95,8 @@ typedef enum {
 } lbpc_thermal_model;
 
 /* Ghost rule at a non-periodic side, used by every stencil: a neighbour
- * outside the lattice takes rho and psi of the nearest lattice node, v = 0
+ * outside the lattice takes rho and psi of the nearest lattice node (psi
+ * from the virtual density of wet_amp / wet_shift across a wall), v = 0
  * at a wall (v of that node at an open side) and T of the crossed side (y
  * side first at corners; the y- wall has T_hot on hot_x0 <= x < hot_x1).
  *
@@ -115,6 +116,11 @@ typedef struct lbpc_config {
   double T_hot;           /* hot-spot temperature on the y- wall */
   double rho_ref, T_ref;  /* references of the shifted storage forms */
   double rho_v, rho_l;    /* coexistence densities for the radius diagnostic */
+  double wet_amp;         /* wall wetting: a ghost across a wall enters the */
+  double wet_shift;       /* interaction force with psi(rho_w, T_n), rho_w =
+                           * (1 + wet_amp) rho_n - wet_shift clamped to
+                           * [0, 0.9/b], n the nearest lattice node; 0 and 0
+                           * give psi_n (neutral); wet_amp > -1, finite */
   int32_t nx, ny;         /* lattice size, each >= 4 */
   int32_t bc[4];          /* lbpc_bc per side */
   int32_t hot_x0, hot_x1; /* hot-spot columns */

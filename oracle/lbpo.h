@@ -72,6 +72,13 @@ typedef struct lbpo_config {
   double T_hot;         /* hot-spot temperature on the y- wall */
   double rho_ref, T_ref;/* shifted-storage references (GPU only; ignored) */
   double rho_v, rho_l;  /* coexistence densities used by the radius diagnostic */
+  /* wetting of wall sides (a reading: the paper names contact angles but no
+   * scheme): the interaction force sees a ghost node across a wall through
+   * psi(rho_w, T_n) with the virtual density rho_w = (1 + wet_amp) rho_n -
+   * wet_shift, clamped to [0, 0.9/b], of the ghost's nearest lattice node n
+   * (rho_n, T_n).  Zero for both is the neutral rule psi = psi_n; wet_amp > 0
+   * makes the wall more wetting, wet_shift > 0 less. */
+  double wet_amp, wet_shift;
   int32_t nx, ny;
   int32_t bc[4];
   int32_t hot_x0, hot_x1;   /* hot spot covers hot_x0 <= x < hot_x1 */

@@ -137,6 +137,11 @@ inline const char* check_config(const lbpc_config* c) {
         !(c->s_g[i] > 0.0 && c->s_g[i] < 2.0))
       return "relaxation rates must lie in (0, 2)";
   if (!(c->G < 0.0)) return "G must be negative";
+  if (!std::isfinite(c->wet_amp) || !(c->wet_amp > -1.0) ||
+      !std::isfinite(c->wet_shift))
+    return "wet_amp must be finite and > -1, wet_shift finite";
+  if (c->wet_amp != 0.0 || c->wet_shift != 0.0)
+    return "wall wetting (wet_amp, wet_shift) is not supported yet";
   if (!(c->a > 0.0 && c->b > 0.0 && c->R > 0.0 && c->cv > 0.0))
     return "a, b, R and cv must be positive";
   if (c->lambda_mode != LBPC_LAMBDA_CONST &&

@@ -57,7 +57,7 @@ def base_config(nx: int, ny: int, **over) -> dict:
         s_f=list(S_F_DEFAULT), s_g=list(S_G_DEFAULT),
         G=-1.0, sigma=SIGMA_DEFAULT, gx=0.0, gy=0.0,
         T_bc=[T_SAT] * 4, T_hot=T_SAT, rho_ref=RHO_V, T_ref=T_SAT,
-        rho_v=RHO_V, rho_l=RHO_L,
+        rho_v=RHO_V, rho_l=RHO_L, wet_amp=0.0, wet_shift=0.0,
         nx=int(nx), ny=int(ny), bc=[BC_PERIODIC] * 4,
         hot_x0=0, hot_x1=0, lambda_mode=LAMBDA_CONST,
         thermal_model=THERMAL_IMPROVED, precision=FP64, flags=0,

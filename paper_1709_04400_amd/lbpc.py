@@ -45,6 +45,7 @@ class Config(ctypes.Structure):
         ("T_bc", ctypes.c_double * 4), ("T_hot", ctypes.c_double),
         ("rho_ref", ctypes.c_double), ("T_ref", ctypes.c_double),
         ("rho_v", ctypes.c_double), ("rho_l", ctypes.c_double),
+        ("wet_amp", ctypes.c_double), ("wet_shift", ctypes.c_double),
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
         ("bc", ctypes.c_int32 * 4),
         ("hot_x0", ctypes.c_int32), ("hot_x1", ctypes.c_int32),
