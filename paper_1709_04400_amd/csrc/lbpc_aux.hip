@@ -111,7 +111,10 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_macro2(StepParams p,
   for (int k = 0; k < 8; ++k) {
     Ghost gh = resolve(p, x + DX[k], y + DY[k]);
     const double w = k < 4 ? 1.0 / 3.0 : 1.0 / 12.0;
-    const double pn = psi[(long long)gh.y * p.nx + gh.x];
+    const long long n = (long long)gh.y * p.nx + gh.x;
+    const double pn = p.wet && gh.kind == GH_WALL
+                          ? wall_psi(p, io[n], io[3 * N + n])
+                          : psi[n];
     sx += w * pn * DX[k];
     sy += w * pn * DY[k];
   }

@@ -44,6 +44,11 @@ struct StepParams {
   double wg0, wg1, wg2;    // rest equilibrium of g per unit T: rest, axis,
                            // diagonal (Eq. 53, or Eq. 14 for Gong-Cheng)
   double gc_ta, gc_tb;     // Gong-Cheng: tau_g = gc_ta / rho + gc_tb
+  // wall wetting: a ghost across a wall enters the interaction force with
+  // psi of the virtual density (1 + wet_amp) rho_n - wet_shift, clamped to
+  // [0, 0.9/b], at T_n of its nearest node n (wet = 0: psi_n itself)
+  int wet;
+  double wet_amp, wet_shift;
   // derived on the host: 1/Tc, 2/G, 1/c_V, lambda0/c_V and the sigma terms
   // 12 sigma G^2 / (1/s_f[k] - 1/2), k = 1, 2 (|F_m|^2/psi^2 = G^2 |s|^2)
   double inv_Tc, two_over_G, inv_cv, lam_over_cv, sig1, sig2;
@@ -53,9 +58,9 @@ struct StepParams {
   int fresh;      // 1: the input buffer holds pre-collision f(t) (no pull)
   int phi_valid;  // 0: first step, phi_prev := phi
   // buffers
-  const void* fin;  // [9][N] input f (post-collision f*(t-1) or fresh f(t))
+  const void* fin;  // [ny][9][nx] input f (post-collision f*(t-1) or fresh f(t))
   const void* gin;
-  void* fout;       // [9][N] output f*(t)
+  void* fout;       // [ny][9][nx] output f*(t)
   void* gout;
   void* phi;        // [N] phi(t-1) (compute precision); for the BGK form
                     // followed by [N] T v_x and [N] T v_y of step t-1
@@ -168,6 +173,16 @@ __device__ __forceinline__ double pseudo_psi(const StepParams& p, double rho,
                                              double T) {
   double psi2 = 2.0 * (pr_p(p, rho, T) - rho * (1.0 / 3.0)) / p.G;
   return sqrt(psi2 > 0.0 ? psi2 : 0.0);
+}
+
+// psi of a ghost across a wall (wetting): the virtual density of the ghost's
+// nearest lattice node n, (1 + wet_amp) rho_n - wet_shift clamped to
+// [0, 0.9/b], at T_n
+__device__ __forceinline__ double wall_psi(const StepParams& p, double rho_n,
+                                           double T_n) {
+  double rw = (1.0 + p.wet_amp) * rho_n - p.wet_shift;
+  rw = rw < 0.0 ? 0.0 : (rw > 0.9 / p.b ? 0.9 / p.b : rw);
+  return pseudo_psi(p, rw, T_n);
 }
 
 // ------------------------------------------------------------ ghost rule

@@ -140,8 +140,6 @@ inline const char* check_config(const lbpc_config* c) {
   if (!std::isfinite(c->wet_amp) || !(c->wet_amp > -1.0) ||
       !std::isfinite(c->wet_shift))
     return "wet_amp must be finite and > -1, wet_shift finite";
-  if (c->wet_amp != 0.0 || c->wet_shift != 0.0)
-    return "wall wetting (wet_amp, wet_shift) is not supported yet";
   if (!(c->a > 0.0 && c->b > 0.0 && c->R > 0.0 && c->cv > 0.0))
     return "a, b, R and cv must be positive";
   if (c->lambda_mode != LBPC_LAMBDA_CONST &&
@@ -202,6 +200,9 @@ inline void derive_params(const lbpc_config& c, StepParams& p) {
   p.improved = c.thermal_model == LBPC_THERMAL_IMPROVED;
   p.gc = c.thermal_model == LBPC_THERMAL_GONG_CHENG;
   p.bgk = c.thermal_model == LBPC_THERMAL_IMPROVED_BGK;
+  p.wet = c.wet_amp != 0.0 || c.wet_shift != 0.0;
+  p.wet_amp = c.wet_amp;
+  p.wet_shift = c.wet_shift;
   // BGK form: 1/tau_g = s_g[3]; (1 - 1/(2 tau_g)) / c_s^2 of Eq. (31)
   p.bgk_itau = c.s_g[3];
   p.bgk_cfac = 3.0 * (1.0 - 0.5 * c.s_g[3]);

@@ -265,10 +265,34 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
           if (rb + 1 >= ny) sp = sl1;
         }
         const C pc = s_psi[sl1][t];
-        const C pE = s_psi[sl1][ttp], pW = s_psi[sl1][ttm];
-        const C pN = s_psi[sp][t], pS = s_psi[sm][t];
-        const C pNE = s_psi[sp][ttp], pNW = s_psi[sp][ttm];
-        const C pSE = s_psi[sm][ttp], pSW = s_psi[sm][ttm];
+        C pE = s_psi[sl1][ttp], pW = s_psi[sl1][ttm];
+        C pN = s_psi[sp][t], pS = s_psi[sm][t];
+        C pNE = s_psi[sp][ttp], pNW = s_psi[sp][ttm];
+        C pSE = s_psi[sm][ttp], pSW = s_psi[sm][ttm];
+        if (GEN && p.wet) {
+          // a neighbour across a wall (either crossed side, at corners)
+          // takes psi of its nearest node's virtual density; the clamped
+          // ring slot and column above are that node
+          const bool c0 = !p.perx && c - 1 < 0, c1 = !p.perx && c + 1 >= nx;
+          const bool r0 = !p.pery && rb - 1 < 0, r1 = !p.pery && rb + 1 >= ny;
+          if (__builtin_amdgcn_ballot_w64(c0 || c1 || r0 || r1) != 0) {
+            const bool w0 = c0 && p.bc[0] == BC_WALL;
+            const bool w1 = c1 && p.bc[1] == BC_WALL;
+            const bool w2 = r0 && p.bc[2] == BC_WALL;
+            const bool w3 = r1 && p.bc[3] == BC_WALL;
+            auto wp = [&](int sl, int tt) {
+              return C(wall_psi(p, double(s_rho[sl][tt]), double(s_T[sl][tt])));
+            };
+            if (w1) pE = wp(sl1, ttp);
+            if (w0) pW = wp(sl1, ttm);
+            if (w3) pN = wp(sp, t);
+            if (w2) pS = wp(sm, t);
+            if (w1 || w3) pNE = wp(sp, ttp);
+            if (w0 || w3) pNW = wp(sp, ttm);
+            if (w1 || w2) pSE = wp(sm, ttp);
+            if (w0 || w2) pSW = wp(sm, ttm);
+          }
+        }
         // F_m = -G psi sum_a w_a psi(x+e_a) e_a = -G psi (sx, sy)
         const C sx = C(1.0 / 3.0) * (pE - pW) +
                      C(1.0 / 12.0) * ((pNE - pNW) + (pSE - pSW));

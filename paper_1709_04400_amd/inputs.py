@@ -178,6 +178,58 @@ def d2_droplet(model=THERMAL_IMPROVED, n=200, diameter=60.0,
     return cfg, fl
 
 
+# wetting parameters (virtual density (1 + wet_amp) rho_n of the wall ghosts)
+# calibrated on a sessile droplet at T_sat (R0 = 13 on 80 x 40, 3000 steps,
+# T frozen): about 108 and 45 degrees, the contact angles of Sec. IV.A (heated
+# surface) and IV.B (boiling).  The multiplicative form is used for both: the
+# subtractive wet_shift thins the vapour next to the wall (rho_n - 0.18 halves
+# the vapour's virtual density), which the coupled thermal step does not
+# survive where a non-wetting wall meets vapour only.
+WET_AMP_108 = -0.13
+WET_AMP_45 = 0.52
+# the heated-surface workload runs at about 95 degrees: with the thermal step
+# coupled, a droplet of radius 40 at 100 degrees or more either lifts off the
+# wall or meets an invalid state within a few thousand steps (radius 13 at 108
+# degrees is stable), so the paper's 108 degrees is not reproduced there
+WET_AMP_SURFACE = -0.04
+CHI_SURFACE = 0.08      # lambda = rho c_V chi of the heated-surface test
+
+
+def sessile_droplet(nx, ny, radius, wet_amp=0.0, wet_shift=0.0, T_w=None,
+                    top=BC_WALL, precision=FP64):
+    """A droplet centred on the y- wall (half of it inside), vapour above, all
+    at T_sat; walls at y- (and y+ unless `top` says open), periodic x; the
+    y- wall held at T_w (default T_sat), the top at T_sat; lambda = rho c_V
+    chi with chi = 0.08 as in the paper's wall cases.  (A constant lambda
+    puts the improved model's excess diffusion (chi - k) lap T, chi =
+    lambda/(rho c_V), into its explicit source term, which is unstable where
+    chi - k > 3/8, i.e. in the thinned vapour next to a non-wetting wall.)"""
+    Tw = T_SAT if T_w is None else T_w
+    cfg = base_config(nx, ny, bc=[BC_PERIODIC, BC_PERIODIC, BC_WALL, top],
+                      T_bc=[T_SAT, T_SAT, Tw, T_SAT], wet_amp=wet_amp,
+                      wet_shift=wet_shift, lambda_mode=LAMBDA_RHO_CV_CHI,
+                      chi=CHI_SURFACE, precision=precision)
+    return cfg, droplet_fields(nx, ny, radius, cx=nx / 2.0, cy=-0.5)
+
+
+def heated_surface(model=THERMAL_IMPROVED, lambda_mode=LAMBDA_RHO_CV_CHI,
+                   nx=300, ny=150, radius=40.0, T_w_over_Tc=0.875,
+                   wet_amp=WET_AMP_SURFACE, precision=FP64):
+    """Droplet evaporation on a heated surface, Sec. IV.A: a 300 x 150
+    lattice, a droplet of radius 40 on the centre of the bottom surface at
+    T_sat = 0.86 Tc in vapour at T_sat,
+    lambda = rho c_V chi with chi = 0.08 (or the constant lambda of the D^2
+    test), nu = 0.1, c_V = 5, periodic x, open top at T_sat.  Returns the
+    configuration of the evaporation stage (bottom wall at T_w = 0.875 Tc);
+    the equilibration stage before it is the same with the wall at T_sat.
+    The wall wets at about 95 degrees (WET_AMP_SURFACE), not the paper's 108."""
+    cfg, fl = sessile_droplet(nx, ny, radius, wet_amp=wet_amp,
+                              T_w=T_w_over_Tc * TC, top=BC_OPEN,
+                              precision=precision)
+    cfg.update(thermal_model=model, lambda_mode=lambda_mode)
+    return cfg, fl
+
+
 def batch_cases(count=256, seed=1709, precision=FP32):
     """The batched evaporation sweep: one heated-wall droplet per draw,
     droplet radius 0.2 x grid size."""
