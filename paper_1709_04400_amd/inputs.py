@@ -230,6 +230,29 @@ def heated_surface(model=THERMAL_IMPROVED, lambda_mode=LAMBDA_RHO_CV_CHI,
     return cfg, fl
 
 
+def boiling(g, nx=150, ny=300, hot=20, T_hot_over_Tc=1.25,
+            wet_amp=WET_AMP_45, precision=FP64):
+    """Bubble nucleation and departure, Sec. IV.B: a 150 x 300 lattice,
+    liquid pool to mid-height below its vapour at T_sat, periodic x, bottom
+    wall at T_sat with a centred hot spot at T_h = 1.25 Tc, top wall at T_sat
+    (a reading), lambda = rho c_V chi with chi = 0.06, contact angle about 45
+    degrees, buoyancy (rho - rho_ave)(0, -g).  The paper heats three wall
+    nodes; the halfway (anti-bounce-back) wall here heats the first fluid row
+    less, and three or twelve hot nodes nucleate no bubble or none that
+    departs at small g, so the default hot spot is 20 nodes wide."""
+    x0 = nx // 2 - hot // 2
+    cfg = base_config(nx, ny, bc=[BC_PERIODIC, BC_PERIODIC, BC_WALL, BC_WALL],
+                      T_bc=[T_SAT] * 4, hot_x0=x0, hot_x1=x0 + hot,
+                      T_hot=T_hot_over_Tc * TC, gy=-g,
+                      lambda_mode=LAMBDA_RHO_CV_CHI, chi=CHI_BUBBLE,
+                      wet_amp=wet_amp, precision=precision)
+    y = np.mgrid[0:ny, 0:nx][0].astype(np.float64)
+    rho = tanh_profile(y - (ny // 2 - 0.5), 5.0, RHO_L, RHO_V)
+    z = np.zeros((ny, nx))
+    return cfg, dict(rho=rho, ux=z.copy(), uy=z.copy(),
+                     T=np.full((ny, nx), T_SAT))
+
+
 def batch_cases(count=256, seed=1709, precision=FP32):
     """The batched evaporation sweep: one heated-wall droplet per draw,
     droplet radius 0.2 x grid size."""

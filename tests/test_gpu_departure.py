@@ -1,0 +1,70 @@
+"""Bubble departure diameter against gravity (Sec. IV.B, Fig. 7): the paper
+fits D_d = 0.209 g^-0.5 to its improved-model runs.  Here one lattice per g
+runs in one batch (one persistent launch per step) with the 45-degree wall of
+the wetting reading; the departure step is the first at which the largest
+vapour region below the initial pool surface, after growing on the hot spot,
+no longer touches the wall row (reading C21), and D = 2 sqrt(A / pi) of that
+region.  What is checked is the trend: every g departs, D falls with g, and
+the log-log slope is -0.5 within the scatter of a five-point fit.  The
+constant is not compared (heating and wetting are readings, see the boiling
+builder)."""
+import json
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+from paper_1709_04400_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+GS = [2.0e-5, 2.5e-5, 3.0e-5, 4.0e-5, 5.0e-5]
+
+
+def _departures(gs, max_steps=60000, every=250):
+    from paper_1709_04400_amd import lbpc
+    cases = [I.boiling(g) for g in gs]
+    b = lbpc.Batch([c for c, _ in cases])
+    for k, (_, f) in enumerate(cases):
+        b.init_fields(k, f["rho"], f["ux"], f["uy"], f["T"])
+    half = 0.5 * (I.RHO_L + I.RHO_V)
+    pool = cases[0][0]["ny"] // 2
+    grown = [False] * len(gs)
+    out = [None] * len(gs)
+    for k in range(max_steps // every):
+        b.step(every)
+        for i in range(len(gs)):
+            if out[i] is not None:
+                continue
+            vap = b.rho_u_T(i)[0][:pool] < half
+            lab, n = ndimage.label(vap)
+            if n == 0:
+                continue
+            sizes = ndimage.sum(vap, lab, range(1, n + 1))
+            for c in np.unique(lab[-1]):   # the vapour above the pool
+                if c:
+                    sizes[c - 1] = 0
+            if sizes.max() == 0:
+                continue
+            big = int(np.argmax(sizes)) + 1
+            touches = bool((lab[0] == big).any())
+            if touches and sizes[big - 1] > 20:
+                grown[i] = True
+            if grown[i] and not touches:
+                out[i] = dict(g=gs[i], step=(k + 1) * every,
+                              D=float(2 * np.sqrt(sizes[big - 1] / np.pi)))
+        if all(o is not None for o in out):
+            break
+    b.close()
+    return out
+
+
+def test_departure_diameter_falls_like_g_to_minus_half():
+    res = _departures(GS)
+    print("\n[departure] " + json.dumps(res), flush=True)
+    assert all(r is not None for r in res), res
+    D = np.array([r["D"] for r in res])
+    assert np.all(np.diff(D) < 0), D
+    slope = np.polyfit(np.log(GS), np.log(D), 1)[0]
+    print(f"[departure] log-log slope {slope:.3f}", flush=True)
+    assert -0.65 < slope < -0.35, slope
