@@ -1,0 +1,98 @@
+"""Parity at the benchmark's full size, in the launch configuration bench.py
+times: the 4096 x 4096 periodic spinodal lattice, default tiles, one launch
+per step.  The oracle cannot step 1.7e7 nodes in a test, so the check is
+local.  One step's outputs at a node depend on the state within three nodes
+(the pull, then the interaction force one node further, then the divergence
+of v in the thermal source one node further still), so a window of the GPU
+state cut out with a margin of four, stepped once by the oracle as a small
+periodic lattice, reproduces the GPU's next state in its interior exactly
+(up to rounding).  Windows sit on strip, row-run and lattice boundaries of
+the FP64 and FP32 tilings and on the periodic wrap; the whole lattice is
+checked against a property that holds at any size (mass conservation)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1709_04400_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+N = 4096
+WIN, MARGIN = 24, 4
+# window centres: strip boundaries of 241-column (FP64) and 252-column (FP32)
+# strips, boundaries of 35-row runs, the lattice corner (periodic wrap), the
+# last strip and run, and the middle
+CENTRES = [(0, 0), (241, 35), (252, 70), (4095, 4095), (3856, 4095),
+           (4032, 2100), (2048, 2047), (1205, 1260)]
+# max relative error of rho and T in the window interiors, and of f and g
+# (relative to their largest magnitude) for FP64; the reduced-precision
+# bounds (and the mass-drift bounds below) are about three times the errors
+# measured when they were set (FP64 6.5e-16; FP32 1.4e-7, FP32 deviations
+# 1.5e-7, FP16 deviations 2.2e-4; mass drift 1e-15, 9e-9, 9e-9, 7.8e-7)
+TOL = {I.FP64: 1e-12, I.FP32: 5e-7, I.FP32_SHIFTED: 5e-7,
+       I.FP16_SHIFTED: 7e-4}
+MASS = {I.FP64: 1e-12, I.FP32: 3e-8, I.FP32_SHIFTED: 3e-8,
+        I.FP16_SHIFTED: 3e-6}
+
+
+def _split(state):
+    w = state.view(np.float64)
+    n = N * N
+    f = w[:9 * n].reshape(9, N, N)
+    g = w[9 * n:18 * n].reshape(9, N, N)
+    phi = w[18 * n:19 * n].reshape(N, N)
+    meta = w[19 * n:19 * n + 3]
+    return f, g, phi, int(meta[:1].view(np.int64)[0]), float(meta[1]), \
+        int(meta[2:3].view(np.int64)[0])
+
+
+def _window(a, cx, cy):
+    ys = (np.arange(cy - WIN // 2, cy + WIN // 2)) % N
+    xs = (np.arange(cx - WIN // 2, cx + WIN // 2)) % N
+    return a[..., ys[:, None], xs[None, :]]
+
+
+@pytest.mark.parametrize("prec", [I.FP64, I.FP32, I.FP32_SHIFTED,
+                                  I.FP16_SHIFTED])
+def test_spinodal_4096_one_step_in_windows(prec):
+    from paper_1709_04400_amd import lbpc
+    cfg, fl = I.spinodal(N, precision=prec)
+    g = lbpc.Simulation(cfg)
+    g.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
+    del fl
+    g.step(20)
+    m0 = g.diag()["mass"]
+    s0 = g.save_state()
+    g.step(1)
+    s1 = g.save_state()
+    m1 = g.diag()["mass"]
+    g.close()
+    print(f"\n[fullsize] prec={prec} mass drift {abs(m1 - m0) / m0:.2e}",
+          flush=True)
+    assert abs(m1 - m0) <= MASS[prec] * m0
+
+    f0, g0, p0, valid, rho_ave, step = _split(s0)
+    f1, g1, _, _, _, _ = _split(s1)
+    ocfg = dict(cfg, nx=WIN, ny=WIN, precision=I.FP64)
+    inner = slice(MARGIN, WIN - MARGIN)
+    worst = 0.0
+    for cx, cy in CENTRES:
+        o = O.Oracle(ocfg)
+        o.set_state({"f": _window(f0, cx, cy), "g": _window(g0, cx, cy),
+                     "phi_prev": _window(p0, cx, cy), "phi_valid": valid,
+                     "rho_ave": rho_ave, "step": step})
+        o.step(1)
+        st = o.get_state()
+        fo = st["f"].reshape(9, WIN, WIN)[:, inner, inner]
+        go = st["g"].reshape(9, WIN, WIN)[:, inner, inner]
+        fg = _window(f1, cx, cy)[:, inner, inner]
+        gg = _window(g1, cx, cy)[:, inner, inner]
+        e_rho = np.abs(fg.sum(0) - fo.sum(0)).max() / np.abs(fo.sum(0)).min()
+        e_T = np.abs(gg.sum(0) - go.sum(0)).max() / np.abs(go.sum(0)).min()
+        worst = max(worst, e_rho, e_T)
+        assert e_rho < TOL[prec] and e_T < TOL[prec], (cx, cy, e_rho, e_T)
+        if prec == I.FP64:
+            assert np.abs(fg - fo).max() < TOL[prec] * np.abs(fo).max()
+            assert np.abs(gg - go).max() < TOL[prec] * np.abs(go).max()
+    print(f"[fullsize] prec={prec} worst window error {worst:.2e}",
+          flush=True)

@@ -525,3 +525,43 @@ def test_d2_law_trend():
     assert slope < 0
     assert corr > 0.97
     assert r2[-1] < 0.8 * r2[0]
+
+
+def test_one_step_dependence_radius_is_three():
+    """One step's outputs at a node depend on the state within three nodes
+    (the pull, the interaction force of the pulled state, then div v of the
+    thermal source): a window of a spinodal state stepped once as its own
+    periodic lattice reproduces the whole lattice's step exactly three or more
+    nodes inside its edge, and not two.  The full-size GPU check relies on
+    this."""
+    n, win = 48, 20
+    cfg, fl = I.spinodal(n)
+    o = O.Oracle(cfg)
+    o.init_fields(**fl)
+    o.step(12)
+    s0 = o.get_state()
+    o.step(1)
+    s1 = o.get_state()
+    ys = np.arange(30 - win // 2, 30 + win // 2) % n
+    xs = np.arange(45 - win // 2, 45 + win // 2) % n
+
+    def cut(a, k):
+        a = a.reshape(k, n, n) if k > 1 else a.reshape(n, n)
+        return a[..., ys[:, None], xs[None, :]]
+
+    w = O.Oracle(dict(cfg, nx=win, ny=win))
+    w.set_state({"f": cut(s0["f"], 9), "g": cut(s0["g"], 9),
+                 "phi_prev": cut(s0["phi_prev"], 1),
+                 "phi_valid": s0["phi_valid"], "rho_ave": s0["rho_ave"],
+                 "step": s0["step"]})
+    w.step(1)
+    sw = w.get_state()
+    diffs = []
+    for m in (2, 3):
+        inner = slice(m, win - m)
+        diffs.append(max(
+            np.abs(sw["f"].reshape(9, win, win)[:, inner, inner] -
+                   cut(s1["f"], 9)[:, inner, inner]).max(),
+            np.abs(sw["g"].reshape(9, win, win)[:, inner, inner] -
+                   cut(s1["g"], 9)[:, inner, inner]).max()))
+    assert diffs[1] == 0.0 and diffs[0] > 0.0, diffs
