@@ -96,3 +96,39 @@ def test_spinodal_4096_one_step_in_windows(prec):
             assert np.abs(gg - go).max() < TOL[prec] * np.abs(go).max()
     print(f"[fullsize] prec={prec} worst window error {worst:.2e}",
           flush=True)
+
+
+# FP32: about three times the error measured when the bound was set
+# (FP64 3.5e-15, FP32 1.67e-6)
+BATCH_TOL = {I.FP64: 1e-11, I.FP32: 5e-6}
+
+
+@pytest.mark.parametrize("prec", [I.FP64, I.FP32])
+def test_full_sweep_batch_sampled_lattices(prec):
+    """The batched workload at its full size: all 256 lattices of the seeded
+    sweep (2.5e7 nodes) in one persistent launch per step with autotuned
+    tiles, as bench.py runs it; after 20 steps the smallest, the largest and
+    four other lattices are compared whole with the oracle."""
+    from paper_1709_04400_amd import lbpc
+    cases = I.batch_cases(count=256, seed=1709, precision=prec)
+    b = lbpc.Batch([c for c, _ in cases])
+    for k, (_, f) in enumerate(cases):
+        b.init_fields(k, f["rho"], f["ux"], f["uy"], f["T"])
+    b.autotune(2)
+    b.step(20)
+    sizes = [c["nx"] * c["ny"] for c, _ in cases]
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 17, 101,
+                   163, 255})
+    worst = 0.0
+    for k in pick:
+        cfg, f = cases[k]
+        o = O.Oracle(dict(cfg, precision=I.FP64))
+        o.init_fields(**f)
+        o.step(20)
+        (r1, ux1, uy1, T1), (r2, ux2, uy2, T2) = b.rho_u_T(k), o.rho_u_T()
+        e = max(np.max(np.abs(r1 - r2) / r2), np.max(np.abs(T1 - T2) / T2))
+        worst = max(worst, e)
+        assert e < BATCH_TOL[prec], (k, cfg["nx"], e)
+    b.close()
+    print(f"\n[fullsize] batch prec={prec} lattices {pick} worst {worst:.2e}",
+          flush=True)
