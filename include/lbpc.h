@@ -180,13 +180,14 @@ lbpc_status lbpc_init_fields(lbpc_handle *h, const double *rho,
  * lbpc_load_state (of a good state) and lbpc_init_fields clear it. */
 lbpc_status lbpc_step(lbpc_handle *h, int64_t n);
 
-/* Tile shape of the step launches: threads per block (64, 128 or 256; the
- * strip is that many columns minus 4 halo columns) and rows per tile (>= 4).
- * Results do not depend on it. */
+/* Tile shape of the step launches: threads per block (64, 128, 256 or 512;
+ * the strip is at most that many columns minus 4 halo columns) and rows per
+ * tile (>= 4).  Results do not depend on it.  Default: 512 (256 for FP16
+ * deviations), rows sized for several blocks per compute unit. */
 lbpc_status lbpc_set_tiles(lbpc_handle *h, int32_t block_width, int32_t rows);
 
 /* Times `steps` launches of each candidate tile shape (block width 64, 128,
- * 256 x rows 4 ... 64) on the current state, keeps the fastest and reports
+ * 256, 512 x rows 4 ... 64) on the current state, keeps the fastest and reports
  * it.  State and phi history are left unchanged (timing launches write phi
  * to scratch).  Blocks until done. */
 lbpc_status lbpc_autotune(lbpc_handle *h, int32_t steps, int32_t *block_width,
@@ -243,7 +244,8 @@ lbpc_status lbpc_batch_create(const lbpc_config *cfgs, int32_t n,
 lbpc_status lbpc_batch_init_fields(lbpc_batch *b, int32_t c,
                                    const double *rho, const double *ux,
                                    const double *uy, const double *T);
-/* Tile shape: threads per block (64, 128 or 256) and rows per tile (>= 4). */
+/* Tile shape: threads per block (64, 128, 256 or 512) and rows per tile
+ * (>= 4). */
 lbpc_status lbpc_batch_set_tiles(lbpc_batch *b, int32_t block_width,
                                  int32_t rows);
 /* Times `steps` launches of each candidate tile shape (block width 64, 128,

@@ -303,7 +303,7 @@ lbpc_status lbpc_batch_create(const lbpc_config* cfgs, int32_t n,
   b->phi_valid = 0;
   b->step = 0;
   b->bw = env_int("LBPC_TILE_BW", 256);
-  if (b->bw != 64 && b->bw != 128 && b->bw != 256) b->bw = 256;
+  if (!valid_block_width(b->bw)) b->bw = 256;
   b->rows = std::max(MIN_ROWS, env_int("LBPC_TILE_H", 32));
   b->graph[0] = b->graph[1] = nullptr;
   // graph replay (on request: eager launches measured faster here) needs a
@@ -355,8 +355,8 @@ lbpc_status lbpc_batch_init_fields(lbpc_batch* b, int32_t c,
 lbpc_status lbpc_batch_set_tiles(lbpc_batch* b, int32_t block_width,
                                  int32_t rows) {
   if (!b) return bfail(nullptr, LBPC_ERR_ARG, "batch is NULL");
-  if (block_width != 64 && block_width != 128 && block_width != 256)
-    return bfail(b, LBPC_ERR_ARG, "block width must be 64, 128 or 256");
+  if (!valid_block_width(block_width))
+    return bfail(b, LBPC_ERR_ARG, "block width must be 64, 128, 256 or 512");
   if (rows < MIN_ROWS) return bfail(b, LBPC_ERR_ARG, "rows must be >= 4");
   BHIP(b, hipStreamSynchronize(b->stream), "synchronise");
   b->bw = block_width;

@@ -286,6 +286,12 @@ inline int tile_grid(int nwork, int prec, int bw) {
   return nwork < cus * per_cu ? nwork : cus * per_cu;
 }
 
+// block widths (threads per block) the step kernels are built for; a strip
+// is that many columns minus the 2 x 2 halo columns
+inline bool valid_block_width(int bw) {
+  return bw == 64 || bw == 128 || bw == 256 || bw == 512;
+}
+
 inline int env_int(const char* name, int dflt) {
   const char* v = std::getenv(name);
   return v ? std::atoi(v) : dflt;

@@ -618,6 +618,8 @@ hipError_t launch_step(const StepParams& p, int prec, hipStream_t s) {
     LBPC_LAUNCH_BW(PR, 64)                                                  \
   } else if (p.bw == 128) {                                                 \
     LBPC_LAUNCH_BW(PR, 128)                                                 \
+  } else if (p.bw == 512) {                                                 \
+    LBPC_LAUNCH_BW(PR, 512)                                                 \
   } else {                                                                  \
     LBPC_LAUNCH_BW(PR, 256)                                                 \
   }
@@ -649,6 +651,8 @@ hipError_t launch_step_batch(const StepParams* table, const void* work,
     LBPC_BLAUNCH_BW(PR, 64)                                                   \
   } else if (bw == 128) {                                                     \
     LBPC_BLAUNCH_BW(PR, 128)                                                  \
+  } else if (bw == 512) {                                                     \
+    LBPC_BLAUNCH_BW(PR, 512)                                                  \
   } else {                                                                    \
     LBPC_BLAUNCH_BW(PR, 256)                                                  \
   }
