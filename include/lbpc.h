@@ -182,8 +182,9 @@ lbpc_status lbpc_step(lbpc_handle *h, int64_t n);
 
 /* Tile shape of the step launches: threads per block (64, 128, 256 or 512;
  * the strip is at most that many columns minus 4 halo columns) and rows per
- * tile (>= 4).  Results do not depend on it.  Default: 512 (256 for FP16
- * deviations), rows sized for several blocks per compute unit. */
+ * tile (>= 4).  Results do not depend on it.  Default: 512 for FP64 and
+ * for the periodic FP32 forms, 256 otherwise; rows sized for several blocks
+ * per compute unit. */
 lbpc_status lbpc_set_tiles(lbpc_handle *h, int32_t block_width, int32_t rows);
 
 /* Times `steps` launches of each candidate tile shape (block width 64, 128,

@@ -252,12 +252,16 @@ lbpc_status lbpc_create(const lbpc_config* cfg, void* dev_workspace,
   {
     // default tile shape; LBPC_TILE_BW and LBPC_TILE_H override it, and
     // lbpc_autotune / lbpc_set_tiles change it
+    h->tiled = !(p.perx && p.pery) || env_int("LBPC_FORCE_TILED", 0);
     // 512-thread blocks (8 waves, one block per CU at 2 waves per SIMD)
     // read half the halo columns of 256-thread strips: at 4096^2 FP64
-    // +3.8 %, FP32 +5 %; the FP16-deviation form, bound by instruction
-    // issue, needs its 3 waves per SIMD and keeps 256 (-16 % at 512)
-    int bw = env_int("LBPC_TILE_BW",
-                     cfg->precision == LBPC_FP16_SHIFTED ? 256 : 512);
+    // +3.8 % (+3.6 % with walls), periodic FP32 +5 %.  The FP32 forms
+    // with non-periodic sides (the heavier boundary-capable kernel, -11 %)
+    // and the FP16-deviation form (bound by instruction issue, -16 %) need
+    // their 3 waves per SIMD and keep 256.
+    const bool wide = cfg->precision == LBPC_FP64 ||
+                      (cfg->precision != LBPC_FP16_SHIFTED && !h->tiled);
+    int bw = env_int("LBPC_TILE_BW", wide ? 512 : 256);
     if (!valid_block_width(bw)) bw = 256;
     int rows = env_int("LBPC_TILE_H", 0);
     if (rows <= 0) {
@@ -275,7 +279,6 @@ lbpc_status lbpc_create(const lbpc_config* cfg, void* dev_workspace,
     // graph replay (on request: eager launches measured faster here) needs
     // a capturable (non-NULL) stream
     h->use_graph = h->stream != nullptr && env_int("LBPC_GRAPH", 0) != 0;
-    h->tiled = !(p.perx && p.pery) || env_int("LBPC_FORCE_TILED", 0);
     set_tiles_impl(h, bw, rows);
   }
   *out = h;
