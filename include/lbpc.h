@@ -27,6 +27,18 @@
  * every call returns an lbpc_status, and lbpc_last_error gives a message.
  * Calls on one handle are not thread-safe; different handles are
  * independent.  Device work is enqueued on the stream given at creation.
+ *
+ * Environment, read when a handle or batch is created (scheduling only:
+ * results never depend on it):
+ *   LBPC_TILE_BW, LBPC_TILE_H      initial block width and rows per tile
+ *   LBPC_XCD_ORDER=0               plain tile order instead of the
+ *                                  XCD-aware one
+ *   LBPC_GRAPH=1, LBPC_BATCH_GRAPH=1   replay steady steps from a captured
+ *                                  hipGraph (needs a non-NULL stream)
+ *   LBPC_PERSISTENT=1              tile-list kernel with one block per
+ *                                  resident slot walking the list
+ *   LBPC_FORCE_TILED=1, LBPC_FORCE_GEN=1   run a periodic lattice through
+ *                                  the tile-list / boundary-capable kernel
  */
 #ifndef LBPC_H
 #define LBPC_H

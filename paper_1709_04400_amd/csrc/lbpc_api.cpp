@@ -37,6 +37,7 @@ struct lbpc_handle {
   // non-periodic lattices run the persistent tile kernel, which reads its
   // parameters from a device table (one entry per buffer parity)
   int tiled;
+  int force_gen;  // LBPC_FORCE_GEN: boundary-capable kernel on periodic sides
   int table_fresh, table_phi_valid, table_valid, table_tuning;
   int nwork, grid;
   StepParams table_host[2];
@@ -200,7 +201,7 @@ lbpc_status launch_now(lbpc_handle* h, bool tuning) {
               static_cast<const StepParams*>(at(h, h->L.table)),
               at(h, h->L.work), h->nwork, h->cur, h->grid, h->cfg.precision,
               p.bw, h->stream,
-              !(p.perx && p.pery) || env_int("LBPC_FORCE_GEN", 0)),
+              !(p.perx && p.pery) || h->force_gen),
           "step kernel");
   return LBPC_OK;
 }
@@ -253,28 +254,9 @@ lbpc_status lbpc_create(const lbpc_config* cfg, void* dev_workspace,
     // default tile shape; LBPC_TILE_BW and LBPC_TILE_H override it, and
     // lbpc_autotune / lbpc_set_tiles change it
     h->tiled = !(p.perx && p.pery) || env_int("LBPC_FORCE_TILED", 0);
-    // 512-thread blocks (8 waves, one block per CU at 2 waves per SIMD)
-    // read half the halo columns of 256-thread strips: at 4096^2 FP64
-    // +3.8 % (+3.6 % with walls), periodic FP32 +5 %.  The FP32 forms
-    // with non-periodic sides (the heavier boundary-capable kernel, -11 %)
-    // and the FP16-deviation form (bound by instruction issue, -16 %) need
-    // their 3 waves per SIMD and keep 256.
-    const bool wide = cfg->precision == LBPC_FP64 ||
-                      (cfg->precision != LBPC_FP16_SHIFTED && !h->tiled);
-    int bw = env_int("LBPC_TILE_BW", wide ? 512 : 256);
-    if (!valid_block_width(bw)) bw = 256;
-    int rows = env_int("LBPC_TILE_H", 0);
-    if (rows <= 0) {
-      // enough blocks to give each of the 256 CUs several, and at least 16
-      // rows per block so the 4-row warm-up stays small
-      const int nbx = (cfg->nx + bw - 2 * lbpc::HALO - 1) /
-                      (bw - 2 * lbpc::HALO);
-      long long want = (2048LL * 256 / bw) / nbx;
-      if (want < 1) want = 1;
-      rows = (int)((cfg->ny + want - 1) / want);
-      if (rows < 16) rows = 16;
-      if (rows > 256) rows = 256;
-    }
+    h->force_gen = env_int("LBPC_FORCE_GEN", 0) != 0;
+    int bw, rows;
+    default_tiles(*cfg, h->tiled != 0, bw, rows);
     p.xcd_order = env_int("LBPC_XCD_ORDER", 1);
     // graph replay (on request: eager launches measured faster here) needs
     // a capturable (non-NULL) stream

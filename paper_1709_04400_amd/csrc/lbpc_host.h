@@ -297,5 +297,31 @@ inline int env_int(const char* name, int dflt) {
   return v ? std::atoi(v) : dflt;
 }
 
+// Default tile shape of a single lattice (LBPC_TILE_BW and LBPC_TILE_H
+// override it; lbpc_autotune and lbpc_set_tiles change it later).
+// 512-thread blocks (8 waves, one block per CU at 2 waves per SIMD) read
+// half the halo columns of 256-thread strips: at 4096^2 FP64 +3.8 % (+3.6 %
+// with walls), periodic FP32 +5 %.  The FP32 forms on non-periodic lattices
+// (the heavier boundary-capable kernel, -11 %) and the FP16-deviation form
+// (bound by instruction issue, -16 %) need their 3 waves per SIMD and keep
+// 256.  Rows: enough tiles to give each of the 256 CUs several, and at
+// least 16 rows per tile so the 4-row warm-up of a run stays small.
+inline void default_tiles(const lbpc_config& c, bool tiled, int& bw,
+                          int& rows) {
+  const bool wide = c.precision == LBPC_FP64 ||
+                    (c.precision != LBPC_FP16_SHIFTED && !tiled);
+  bw = env_int("LBPC_TILE_BW", wide ? 512 : 256);
+  if (!valid_block_width(bw)) bw = 256;
+  rows = env_int("LBPC_TILE_H", 0);
+  if (rows <= 0) {
+    const int nbx = (c.nx + bw - 2 * lbpc::HALO - 1) / (bw - 2 * lbpc::HALO);
+    long long want = (2048LL * 256 / bw) / nbx;
+    if (want < 1) want = 1;
+    rows = (int)((c.ny + want - 1) / want);
+    if (rows < 16) rows = 16;
+    if (rows > 256) rows = 256;
+  }
+}
+
 }  // namespace lbpc_host
 
