@@ -136,7 +136,7 @@ void set_tiles_impl(lbpc_handle* h, int bw, int rows) {
   drop_graphs(h);
   StepParams& p = h->base;
   p.bw = bw;
-  strip_shape(h->cfg.nx, bw, h->cfg.precision == LBPC_FP64, p.nbx, p.W);
+  strip_shape(h->cfg.nx, bw, balanced_strips(h->cfg.precision, bw), p.nbx, p.W);
   p.H = rows;
   p.nby = (h->cfg.ny + p.H - 1) / p.H;
   if (h->tiled) {

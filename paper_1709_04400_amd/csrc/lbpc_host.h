@@ -70,6 +70,13 @@ struct Layout {
 // strip to a nearly idle block; measured at 4096^2 they speed up the FP64
 // step (+1.6 %) and mixed-size batches (+1 %) but slow the single-lattice
 // FP32 forms (-2 to -4.5 %), which therefore keep full strips.
+// Single lattices: balanced strips for FP64, and for any form with 512-thread
+// blocks, where a full split leaves a nearly empty last strip (4096 columns:
+// 8 x 508 + 32); FP32 at 512 ran +1.4 % balanced, FP32 deviations +0.7 %.
+inline bool balanced_strips(int precision, int bw) {
+  return precision == LBPC_FP64 || bw == 512;
+}
+
 inline void strip_shape(int nx, int bw, bool balanced, int& nbx, int& W) {
   const int wmax = bw - 2 * lbpc::HALO;
   nbx = (nx + wmax - 1) / wmax;
