@@ -255,8 +255,12 @@ lbpc_status lbpc_create(const lbpc_config* cfg, void* dev_workspace,
     // lbpc_autotune / lbpc_set_tiles change it
     h->tiled = !(p.perx && p.pery) || env_int("LBPC_FORCE_TILED", 0);
     h->force_gen = env_int("LBPC_FORCE_GEN", 0) != 0;
-    int bw, rows;
-    default_tiles(*cfg, h->tiled != 0, bw, rows);
+    int bw, rows, dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                  dev);
+    if (cus < 1) cus = 256;
+    default_tiles(*cfg, h->tiled != 0, cus, bw, rows);
     p.xcd_order = env_int("LBPC_XCD_ORDER", 1);
     // graph replay (on request: eager launches measured faster here) needs
     // a capturable (non-NULL) stream

@@ -304,6 +304,41 @@ inline int env_int(const char* name, int dflt) {
   return v ? std::atoi(v) : dflt;
 }
 
+// Blocks of the step kernel resident per CU: the waves-per-SIMD budget the
+// kernel is compiled for (2 for FP64, 3 for the FP32 forms) over the block's
+// waves, capped by its LDS (5 rings x 5 fields, plus the g ring of the FP32
+// forms' two-row prefetch) against the CU's 160 KiB.
+inline int blocks_per_cu(int precision, int bw) {
+  const bool fp64 = precision == LBPC_FP64;
+  const int by_waves = 4 * (fp64 ? 2 : 3) / (bw / 64);
+  const int lds = fp64 ? 25 * 8 * bw : 25 * 4 * bw + 27 * 4 * bw;
+  const int by_lds = 160 * 1024 / lds;
+  const int n = by_waves < by_lds ? by_waves : by_lds;
+  return n < 1 ? 1 : n;
+}
+
+// Rows per tile for nbx strips: a tile's block marches rows + 4 row
+// iterations, and the tiles run in ceil(tiles / slots) waves, so the time
+// goes as waves x (rows + 4).  Minimised over rows >= 16 this prefers the
+// tallest runs whose tile count just fits a whole number of waves (4096^2
+// FP64 with 512-thread blocks: 147 rows, 252 tiles in one wave of 256
+// slots, 16.26k MLUPS against 15.83k for 37 rows in 3.9 waves; the model
+// ranks all ten heights measured there in order).
+inline int fill_rows(int ny, int nbx, long long slots) {
+  int best_rows = ny < 16 ? ny : 16;
+  long long best = -1;
+  for (int rows = best_rows; rows <= ny; ++rows) {
+    const long long nby = (ny + rows - 1) / rows;
+    const long long waves = (nbx * nby + slots - 1) / slots;
+    const long long cost = waves * (rows + 4);
+    if (best < 0 || cost < best) {
+      best = cost;
+      best_rows = rows;
+    }
+  }
+  return best_rows;
+}
+
 // Default tile shape of a single lattice (LBPC_TILE_BW and LBPC_TILE_H
 // override it; lbpc_autotune and lbpc_set_tiles change it later).
 // 512-thread blocks (8 waves, one block per CU at 2 waves per SIMD) read
@@ -311,9 +346,8 @@ inline int env_int(const char* name, int dflt) {
 // with walls), periodic FP32 +5 %.  The FP32 forms on non-periodic lattices
 // (the heavier boundary-capable kernel, -11 %) and the FP16-deviation form
 // (bound by instruction issue, -16 %) need their 3 waves per SIMD and keep
-// 256.  Rows: enough tiles to give each of the 256 CUs several, and at
-// least 16 rows per tile so the 4-row warm-up of a run stays small.
-inline void default_tiles(const lbpc_config& c, bool tiled, int& bw,
+// 256.  Rows: the wave-filling height of fill_rows for the device's CUs.
+inline void default_tiles(const lbpc_config& c, bool tiled, int cus, int& bw,
                           int& rows) {
   const bool wide = c.precision == LBPC_FP64 ||
                     (c.precision != LBPC_FP16_SHIFTED && !tiled);
@@ -321,12 +355,10 @@ inline void default_tiles(const lbpc_config& c, bool tiled, int& bw,
   if (!valid_block_width(bw)) bw = 256;
   rows = env_int("LBPC_TILE_H", 0);
   if (rows <= 0) {
-    const int nbx = (c.nx + bw - 2 * lbpc::HALO - 1) / (bw - 2 * lbpc::HALO);
-    long long want = (2048LL * 256 / bw) / nbx;
-    if (want < 1) want = 1;
-    rows = (int)((c.ny + want - 1) / want);
-    if (rows < 16) rows = 16;
-    if (rows > 256) rows = 256;
+    int nbx, W;
+    strip_shape(c.nx, bw, balanced_strips(c.precision, bw), nbx, W);
+    rows = fill_rows(c.ny, nbx,
+                     (long long)cus * blocks_per_cu(c.precision, bw));
   }
 }
 
