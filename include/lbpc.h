@@ -195,13 +195,14 @@ lbpc_status lbpc_step(lbpc_handle *h, int64_t n);
 /* Tile shape of the step launches: threads per block (64, 128, 256 or 512;
  * the strip is at most that many columns minus 4 halo columns) and rows per
  * tile (>= 4).  Results do not depend on it.  Default: 512 for FP64 and
- * for the periodic FP32 forms, 256 otherwise; rows sized for several blocks
- * per compute unit. */
+ * for the periodic FP32 forms, 256 otherwise; rows: 20 for the FP32 forms
+ * on a lattice with a non-periodic side, otherwise the height that makes the
+ * tile count just fill a whole number of waves of resident blocks. */
 lbpc_status lbpc_set_tiles(lbpc_handle *h, int32_t block_width, int32_t rows);
 
-/* Times `steps` launches of each candidate tile shape (block width 64, 128,
- * 256, 512 x rows 4 ... 64) on the current state, keeps the fastest and reports
- * it.  State and phi history are left unchanged (timing launches write phi
+/* Times `steps` launches of each candidate tile shape (the shape in place;
+ * block width 64, 128, 256, 512 x rows 4 ... 64 and that width's default
+ * rows) on the current state, keeps the fastest and reports it.  State and phi history are left unchanged (timing launches write phi
  * to scratch).  Blocks until done. */
 lbpc_status lbpc_autotune(lbpc_handle *h, int32_t steps, int32_t *block_width,
                           int32_t *rows, double *ms_per_step);

@@ -7,10 +7,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <string>
-#include <vector>
-
 #include <array>
+#include <string>
 #include <vector>
 
 #include "lbpc_host.h"
@@ -38,6 +36,7 @@ struct lbpc_handle {
   // parameters from a device table (one entry per buffer parity)
   int tiled;
   int force_gen;  // LBPC_FORCE_GEN: boundary-capable kernel on periodic sides
+  int cus;        // compute units of the device (default tile heights)
   int table_fresh, table_phi_valid, table_valid, table_tuning;
   int nwork, grid;
   StepParams table_host[2];
@@ -260,6 +259,7 @@ lbpc_status lbpc_create(const lbpc_config* cfg, void* dev_workspace,
       (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
                                   dev);
     if (cus < 1) cus = 256;
+    h->cus = cus;
     default_tiles(*cfg, h->tiled != 0, cus, bw, rows);
     p.xcd_order = env_int("LBPC_XCD_ORDER", 1);
     // graph replay (on request: eager launches measured faster here) needs
@@ -371,34 +371,42 @@ lbpc_status lbpc_autotune(lbpc_handle* h, int32_t steps, int32_t* block_width,
   if (!h->initialised) return fail(h, LBPC_ERR_STATE, "autotune before init");
   static const int CBW[4] = {64, 128, 256, 512};
   static const int CH[7] = {4, 8, 16, 24, 32, 48, 64};
+  // candidates: the shape in place, then per block width its default height
+  // and the fixed heights
+  std::vector<std::array<int, 2>> cand{{h->base.bw, h->base.H}};
+  for (int bw : CBW) {
+    cand.push_back({bw, default_rows(h->cfg, h->tiled != 0, h->cus, bw)});
+    for (int r : CH)
+      if (r <= h->cfg.ny) cand.push_back({bw, r});
+  }
   hipEvent_t e0, e1;
   HIP_TRY(h, hipEventCreate(&e0), "event");
   HIP_TRY(h, hipEventCreate(&e1), "event");
   float best = 1e30f;
   int best_bw = h->base.bw, best_rows = h->base.H;
   lbpc_status st = LBPC_OK;
-  for (int bw : CBW) {
-    for (int r : CH) {
-      if (r > h->cfg.ny) continue;
-      set_tiles_impl(h, bw, r);
-      st = enqueue_step(h, true);  // warm-up (and uploads)
-      if (st != LBPC_OK) break;
-      hipError_t e = hipEventRecord(e0, h->stream);
-      for (int k = 0; k < steps && st == LBPC_OK; ++k)
-        st = enqueue_step(h, true);
-      if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess && st == LBPC_OK) st = hip_fail(h, e, "timing");
-      if (st != LBPC_OK) break;
-      if (ms < best) {
-        best = ms;
-        best_bw = bw;
-        best_rows = r;
-      }
-    }
+  for (size_t k = 0; k < cand.size(); ++k) {
+    const int bw = cand[k][0], r = cand[k][1];
+    bool seen = false;
+    for (size_t j = 0; j < k; ++j) seen = seen || cand[j] == cand[k];
+    if (seen) continue;
+    set_tiles_impl(h, bw, r);
+    st = enqueue_step(h, true);  // warm-up (and uploads)
     if (st != LBPC_OK) break;
+    hipError_t e = hipEventRecord(e0, h->stream);
+    for (int s = 0; s < steps && st == LBPC_OK; ++s)
+      st = enqueue_step(h, true);
+    if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess && st == LBPC_OK) st = hip_fail(h, e, "timing");
+    if (st != LBPC_OK) break;
+    if (ms < best) {
+      best = ms;
+      best_bw = bw;
+      best_rows = r;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -22,7 +22,7 @@ struct WorkItem {  // mirrors the device-side work item
 
 // candidate tile shapes of the autotuner
 constexpr int CAND_BW[3] = {64, 128, 256};
-constexpr int CAND_H[5] = {16, 24, 32, 48, 64};
+constexpr int CAND_H[6] = {16, 20, 24, 32, 48, 64};
 constexpr int MIN_ROWS = 4;
 
 struct CaseLayout {

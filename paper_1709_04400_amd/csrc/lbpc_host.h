@@ -339,6 +339,21 @@ inline int fill_rows(int ny, int nbx, long long slots) {
   return best_rows;
 }
 
+// Default rows per tile of a single lattice for block width bw.  Periodic
+// lattices and FP64: the wave-filling height of fill_rows for the device's
+// CUs.  The FP32 forms on non-periodic lattices (the boundary-capable tile
+// kernel, 256-thread blocks, three per CU) run fastest with short tiles,
+// against the model: on a 4096^2 lattice walled on all four sides, 20 rows
+// against the wave-filling 92 gave FP32 27.3k against 24.8k MLUPS, FP32
+// deviations 25.4k against 23.7k, FP16 deviations 31.4k against 30.3k, with
+// 16 and 24 rows within 3 % of 20.  (FP64 there: 37 and 147 rows within 1 %.)
+inline int default_rows(const lbpc_config& c, bool tiled, int cus, int bw) {
+  if (tiled && c.precision != LBPC_FP64) return c.ny < 20 ? c.ny : 20;
+  int nbx, W;
+  strip_shape(c.nx, bw, balanced_strips(c.precision, bw), nbx, W);
+  return fill_rows(c.ny, nbx, (long long)cus * blocks_per_cu(c.precision, bw));
+}
+
 // Default tile shape of a single lattice (LBPC_TILE_BW and LBPC_TILE_H
 // override it; lbpc_autotune and lbpc_set_tiles change it later).
 // 512-thread blocks (8 waves, one block per CU at 2 waves per SIMD) read
@@ -346,7 +361,7 @@ inline int fill_rows(int ny, int nbx, long long slots) {
 // with walls), periodic FP32 +5 %.  The FP32 forms on non-periodic lattices
 // (the heavier boundary-capable kernel, -11 %) and the FP16-deviation form
 // (bound by instruction issue, -16 %) need their 3 waves per SIMD and keep
-// 256.  Rows: the wave-filling height of fill_rows for the device's CUs.
+// 256.
 inline void default_tiles(const lbpc_config& c, bool tiled, int cus, int& bw,
                           int& rows) {
   const bool wide = c.precision == LBPC_FP64 ||
@@ -354,12 +369,7 @@ inline void default_tiles(const lbpc_config& c, bool tiled, int cus, int& bw,
   bw = env_int("LBPC_TILE_BW", wide ? 512 : 256);
   if (!valid_block_width(bw)) bw = 256;
   rows = env_int("LBPC_TILE_H", 0);
-  if (rows <= 0) {
-    int nbx, W;
-    strip_shape(c.nx, bw, balanced_strips(c.precision, bw), nbx, W);
-    rows = fill_rows(c.ny, nbx,
-                     (long long)cus * blocks_per_cu(c.precision, bw));
-  }
+  if (rows <= 0) rows = default_rows(c, tiled, cus, bw);
 }
 
 }  // namespace lbpc_host
