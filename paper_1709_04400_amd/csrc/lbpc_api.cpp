@@ -319,7 +319,7 @@ lbpc_status lbpc_step(lbpc_handle* h, int64_t n) {
       if (st != LBPC_OK) return st;
       hipGraphExec_t& g = h->graph[h->cur];
       if (!g) {
-        hipGraph_t graph;
+        hipGraph_t graph = nullptr;
         HIP_TRY(h,
                 hipStreamBeginCapture(h->stream,
                                       hipStreamCaptureModeThreadLocal),
@@ -330,11 +330,13 @@ lbpc_status lbpc_step(lbpc_handle* h, int64_t n) {
         lbpc_status st2 = st == LBPC_OK ? launch_now(h, false) : st;
         h->cur = keep;
         hipError_t e = hipStreamEndCapture(h->stream, &graph);
+        if (e == hipSuccess && st2 == LBPC_OK)
+          e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
+        // the captured graph is not needed once instantiated, nor on failure
+        if (graph) (void)hipGraphDestroy(graph);
         if (st2 != LBPC_OK) return st2;
+        if (e != hipSuccess) g = nullptr;
         HIP_TRY(h, e, "graph capture");
-        HIP_TRY(h, hipGraphInstantiate(&g, graph, nullptr, nullptr, 0),
-                "graph instantiate");
-        (void)hipGraphDestroy(graph);
       }
       const int64_t pairs = n / 2;
       for (int64_t k = 0; k < pairs; ++k)

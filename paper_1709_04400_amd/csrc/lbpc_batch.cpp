@@ -441,17 +441,19 @@ lbpc_status lbpc_batch_step(lbpc_batch* b, int64_t n) {
     if (steady && b->use_graph && n >= 2) {
       hipGraphExec_t& g = b->graph[b->cur];
       if (!g) {
-        hipGraph_t graph;
+        hipGraph_t graph = nullptr;
         BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal),
              "graph capture");
         lbpc_status st = launch(b, b->cur);
         lbpc_status st2 = st == LBPC_OK ? launch(b, 1 - b->cur) : st;
         hipError_t e = hipStreamEndCapture(b->stream, &graph);
+        if (e == hipSuccess && st2 == LBPC_OK)
+          e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
+        // the captured graph is not needed once instantiated, nor on failure
+        if (graph) (void)hipGraphDestroy(graph);
         if (st2 != LBPC_OK) return st2;
+        if (e != hipSuccess) g = nullptr;
         BHIP(b, e, "graph capture");
-        BHIP(b, hipGraphInstantiate(&g, graph, nullptr, nullptr, 0),
-             "graph instantiate");
-        (void)hipGraphDestroy(graph);
       }
       const int64_t pairs = n / 2;
       for (int64_t k = 0; k < pairs; ++k)

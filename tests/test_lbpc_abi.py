@@ -70,7 +70,9 @@ def test_workspace_bytes_and_validation():
     assert n >= 4 * 9 * 100 * 100 * 8 + 100 * 100 * 8
     cfg16 = dict(cfg, precision=I.FP16_SHIFTED)
     assert lb.lbpc_workspace_bytes(cfg16) < n
-    bad = [dict(cfg, nx=3), dict(cfg, bc=[0, 1, 0, 0]), dict(cfg, G=1.0),
+    # too small, more than 2^31 nodes, unpaired periodic side, ...
+    bad = [dict(cfg, nx=3), dict(cfg, ny=3), dict(cfg, nx=65536, ny=32769),
+           dict(cfg, bc=[0, 1, 0, 0]), dict(cfg, G=1.0),
            dict(cfg, s_f=[1.0] * 8 + [2.5]), dict(cfg, precision=7),
            dict(cfg, lambda_mode=5)]
     for b in bad:
