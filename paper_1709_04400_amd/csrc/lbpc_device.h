@@ -148,6 +148,15 @@ __device__ __forceinline__ double w_rest(const StepParams& p, int a) {
   return a == 0 ? p.wg0 : (a < 5 ? p.wg1 : p.wg2);
 }
 
+// 1/x: IEEE division in FP64; the hardware reciprocal (within 1 ulp) in the
+// FP32 arithmetic of the reduced-precision forms, which saves the ~10
+// instructions of a correctly rounded division per use in kernels bound by
+// instruction issue
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float recip(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+
 // ---------------------------------------------------------- EOS, Eq. (56)
 
 __device__ __forceinline__ double pr_p(const StepParams& p, double rho,

@@ -234,7 +234,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
         const float s = 1.0f + float(p.kappa) * (1.0f - sq);
         const float brho = float(p.b) * rho;
         const float D1 = 1.0f - brho, D2 = 1.0f + brho * (2.0f - brho);
-        const float inv = 1.0f / (D1 * D2);
+        const float inv = recip(D1 * D2);
         const double rd = rho;
         const double rRT = rd * p.R * (double)T * (double)D2;
         const double ar2 = p.a * rd * rd * (double)D1;
@@ -303,7 +303,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
         const C rho = s_rho[sl1][t];
         const C drho = rho - C(p.rho_ave);
         const C Fx = Fmx + drho * C(p.gx), Fy = Fmy + drho * C(p.gy);
-        irn = C(1) / rho;
+        irn = recip(rho);
         const C vx = (jx1 + C(0.5) * Fx) * irn;
         const C vy = (jy1 + C(0.5) * Fy) * irn;
         s_vx[sl1][t] = vx;
@@ -489,7 +489,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
           // d_t(T v) = T v(t) - T v(t-1) (history after phi in the array)
           C itau, base, q2, src, cf = C(0), dx = C(0), dy = C(0);
           if (p.gc) {
-            itau = C(1) / (C(p.gc_ta) * irq + C(p.gc_tb));
+            itau = recip(C(p.gc_ta) * irq + C(p.gc_tb));
             base = C(1) - C(1.5) * (vx * vx + vy * vy);
             q2 = C(4.5);
             src = phi;
