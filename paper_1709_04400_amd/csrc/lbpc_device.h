@@ -148,13 +148,16 @@ __device__ __forceinline__ double w_rest(const StepParams& p, int a) {
   return a == 0 ? p.wg0 : (a < 5 ? p.wg1 : p.wg2);
 }
 
-// 1/x: IEEE division in FP64; the hardware reciprocal (within 1 ulp) in the
-// FP32 arithmetic of the reduced-precision forms, which saves the ~10
-// instructions of a correctly rounded division per use in kernels bound by
-// instruction issue
+// 1/x and sqrt(x): IEEE division and square root in FP64; in the FP32
+// arithmetic of the reduced-precision forms the hardware's reciprocal and
+// square root (each within 1 ulp), which save the ~10 and ~14 instructions of
+// the correctly rounded forms per use in kernels bound by instruction issue
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 __device__ __forceinline__ float recip(float x) {
   return __builtin_amdgcn_rcpf(x);
+}
+__device__ __forceinline__ float fsqrt(float x) {
+  return __builtin_amdgcn_sqrtf(x);
 }
 
 // ---------------------------------------------------------- EOS, Eq. (56)

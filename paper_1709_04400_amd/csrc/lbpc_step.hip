@@ -230,7 +230,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
         // FP32 arithmetic: the smooth factors (sqrt(T/Tc), s, 1/(D1 D2))
         // in FP32, the cancelling combinations (repulsive - attractive
         // pressure, then p - rho c_s^2) in FP64
-        const float sq = sqrtf(T * float(p.inv_Tc));
+        const float sq = fsqrt(T * float(p.inv_Tc));
         const float s = 1.0f + float(p.kappa) * (1.0f - sq);
         const float brho = float(p.b) * rho;
         const float D1 = 1.0f - brho, D2 = 1.0f + brho * (2.0f - brho);
@@ -241,7 +241,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
         const double th = (double)s * (double)s;
         const double pe = (rRT - ar2 * th) * (double)inv;
         const double psi2 = p.two_over_G * (pe - rd * (1.0 / 3.0));
-        psi = sqrtf(float(psi2 > 0.0 ? psi2 : 0.0));
+        psi = fsqrt(float(psi2 > 0.0 ? psi2 : 0.0));
         tdpn = C((rRT + ar2 * (p.kappa * (double)(s * sq))) * (double)inv);
         valid = psi2 >= 0.0 && rd > 0.0 && rd * p.b < 1.0 && T - T == 0.0f;
       }
