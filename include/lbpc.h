@@ -27,6 +27,10 @@
  * every call returns an lbpc_status, and lbpc_last_error gives a message.
  * Calls on one handle are not thread-safe; different handles are
  * independent.  Device work is enqueued on the stream given at creation.
+ * A handle (or batch) belongs to one device, the one holding its workspace
+ * and stream: make it the current device (hipSetDevice) for every call on
+ * it, creation included (the tile defaults, events and the host-mapped state
+ * flag are taken on the current device).
  *
  * Environment, read when a handle or batch is created (scheduling only:
  * results never depend on it):

@@ -244,22 +244,31 @@ class Simulation:
         self.nx, self.ny = int(cfg["nx"]), int(cfg["ny"])
         self.device = torch.device(device)
         nbytes = lbpc_workspace_bytes(cfg)
-        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8,
-                              device=self.device)
-        ptr = self.ws.data_ptr()
-        ptr = (ptr + 255) // 256 * 256
-        self.stream = stream if stream is not None else \
-            torch.cuda.Stream(self.device)
-        self.h = lbpc_create(cfg, ptr, nbytes, self.stream.cuda_stream)
+        with self._on():
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8,
+                                  device=self.device)
+            ptr = self.ws.data_ptr()
+            ptr = (ptr + 255) // 256 * 256
+            self.stream = stream if stream is not None else \
+                torch.cuda.Stream(self.device)
+            self.h = lbpc_create(cfg, ptr, nbytes, self.stream.cuda_stream)
+
+    def _on(self):
+        """Every library call on the handle runs with its device current."""
+        import torch
+        return torch.cuda.device(self.device)
 
     def init_fields(self, rho, ux, uy, T):
-        lbpc_init_fields(self.h, rho, ux, uy, T)
+        with self._on():
+            lbpc_init_fields(self.h, rho, ux, uy, T)
 
     def step(self, n: int = 1):
-        lbpc_step(self.h, n)
+        with self._on():
+            lbpc_step(self.h, n)
 
     def rho_u_T(self):
-        return lbpc_get_rho_u_T(self.h, (self.ny, self.nx))
+        with self._on():
+            return lbpc_get_rho_u_T(self.h, (self.ny, self.nx))
 
     def set_tiles(self, block_width, rows):
         _check(lib().lbpc_set_tiles(self.h, int(block_width), int(rows)),
@@ -268,14 +277,16 @@ class Simulation:
     def autotune(self, steps=3):
         bw, rows = ctypes.c_int32(), ctypes.c_int32()
         ms = ctypes.c_double()
-        _check(lib().lbpc_autotune(self.h, int(steps), ctypes.byref(bw),
-                                   ctypes.byref(rows), ctypes.byref(ms)),
-               self.h)
+        with self._on():
+            _check(lib().lbpc_autotune(self.h, int(steps), ctypes.byref(bw),
+                                       ctypes.byref(rows), ctypes.byref(ms)),
+                   self.h)
         return {"block_width": bw.value, "rows": rows.value,
                 "ms_per_step": ms.value}
 
     def diag(self) -> dict:
-        return lbpc_get_diag(self.h)
+        with self._on():
+            return lbpc_get_diag(self.h)
 
     def run(self, steps: int, every: int, log=None) -> list:
         """Advances `steps` steps, taking the FP64 diagnostics after every
@@ -292,14 +303,17 @@ class Simulation:
         return out
 
     def save_state(self) -> np.ndarray:
-        return lbpc_save_state(self.h)
+        with self._on():
+            return lbpc_save_state(self.h)
 
     def load_state(self, buf):
-        lbpc_load_state(self.h, buf)
+        with self._on():
+            lbpc_load_state(self.h, buf)
 
     def close(self):
         if getattr(self, "h", None):
-            lbpc_destroy(self.h)
+            with self._on():
+                lbpc_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -346,18 +360,24 @@ class Batch:
         self.device = torch.device(device)
         arr = _config_array(self.cfgs)
         nbytes = lbpc_batch_workspace_bytes(self.cfgs)
-        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8,
-                              device=self.device)
-        ptr = (self.ws.data_ptr() + 255) // 256 * 256
-        self.stream = stream if stream is not None else \
-            torch.cuda.Stream(self.device)
         h = ctypes.c_void_p()
-        _bcheck(lib().lbpc_batch_create(arr, len(self.cfgs),
-                                        ctypes.c_void_p(ptr), nbytes,
-                                        ctypes.c_void_p(
-                                            self.stream.cuda_stream),
-                                        ctypes.byref(h)))
+        with self._on():
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8,
+                                  device=self.device)
+            ptr = (self.ws.data_ptr() + 255) // 256 * 256
+            self.stream = stream if stream is not None else \
+                torch.cuda.Stream(self.device)
+            _bcheck(lib().lbpc_batch_create(arr, len(self.cfgs),
+                                            ctypes.c_void_p(ptr), nbytes,
+                                            ctypes.c_void_p(
+                                                self.stream.cuda_stream),
+                                            ctypes.byref(h)))
         self.h = h
+
+    def _on(self):
+        """Every library call on the batch runs with its device current."""
+        import torch
+        return torch.cuda.device(self.device)
 
     def __len__(self):
         return len(self.cfgs)
@@ -365,8 +385,9 @@ class Batch:
     def init_fields(self, c, rho, ux, uy, T):
         arrs = [np.ascontiguousarray(a, dtype=np.float64)
                 for a in (rho, ux, uy, T)]
-        _bcheck(lib().lbpc_batch_init_fields(self.h, int(c), *map(_dp, arrs)),
-                self.h)
+        with self._on():
+            _bcheck(lib().lbpc_batch_init_fields(self.h, int(c),
+                                                 *map(_dp, arrs)), self.h)
 
     def set_tiles(self, block_width, rows):
         _bcheck(lib().lbpc_batch_set_tiles(self.h, int(block_width),
@@ -375,26 +396,31 @@ class Batch:
     def autotune(self, steps=3):
         bw, rows = ctypes.c_int32(), ctypes.c_int32()
         ms = ctypes.c_double()
-        _bcheck(lib().lbpc_batch_autotune(self.h, int(steps),
-                                          ctypes.byref(bw), ctypes.byref(rows),
-                                          ctypes.byref(ms)), self.h)
+        with self._on():
+            _bcheck(lib().lbpc_batch_autotune(self.h, int(steps),
+                                              ctypes.byref(bw),
+                                              ctypes.byref(rows),
+                                              ctypes.byref(ms)), self.h)
         return {"block_width": bw.value, "rows": rows.value,
                 "ms_per_step": ms.value}
 
     def step(self, n=1):
-        _bcheck(lib().lbpc_batch_step(self.h, int(n)), self.h)
+        with self._on():
+            _bcheck(lib().lbpc_batch_step(self.h, int(n)), self.h)
 
     def rho_u_T(self, c):
         cfg = self.cfgs[c]
         out = [np.empty((cfg["ny"], cfg["nx"])) for _ in range(4)]
-        _bcheck(lib().lbpc_batch_get_rho_u_T(self.h, int(c), *map(_dp, out)),
-                self.h)
+        with self._on():
+            _bcheck(lib().lbpc_batch_get_rho_u_T(self.h, int(c),
+                                                 *map(_dp, out)), self.h)
         return tuple(out)
 
     def diag(self, c) -> dict:
         d = Diag()
-        _bcheck(lib().lbpc_batch_get_diag(self.h, int(c), ctypes.byref(d)),
-                self.h)
+        with self._on():
+            _bcheck(lib().lbpc_batch_get_diag(self.h, int(c),
+                                              ctypes.byref(d)), self.h)
         return {n: getattr(d, n) for n, _ in Diag._fields_ if n != "pad"}
 
     def run(self, steps: int, every: int, log=None) -> list:
@@ -420,7 +446,8 @@ class Batch:
 
     def close(self):
         if getattr(self, "h", None):
-            lib().lbpc_batch_destroy(self.h)
+            with self._on():
+                lib().lbpc_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):
