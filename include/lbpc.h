@@ -8,7 +8,8 @@
  * units, dx = dt = c = 1, c_s^2 = 1/3):
  *   - density rho, momentum j and temperature T = sum_a g_a (Sec. III.A);
  *   - the Peng-Robinson p_EOS(rho, T) of Eq. (56) and the pseudopotential
- *     psi = sqrt(2 (p_EOS - rho c_s^2) / G), always in FP64;
+ *     psi = sqrt(2 (p_EOS - rho c_s^2) / G), its cancelling differences
+ *     always in FP64;
  *   - the interaction force -G psi(x) sum_a w_a psi(x + e_a) e_a plus the
  *     buoyancy (rho - rho_ave) g of Sec. IV.B; v = (j + F/2) / rho;
  *   - the flow MRT collision with the pseudopotential forcing scheme the
@@ -67,7 +68,9 @@ typedef enum {
 } lbpc_status;
 
 /* storage precision of the distributions (arithmetic: FP64 for FP64, FP32
- * otherwise; psi(rho, T) and the diagnostic sums are always FP64).  The
+ * otherwise, whose reciprocals and square roots are the hardware's, within
+ * 1 ulp; the EOS's cancelling differences, repulsive minus attractive
+ * pressure and p - rho c_s^2, and the diagnostic sums are always FP64).  The
  * shifted forms store f_a - w_a rho_ref and g_a - wg_a T_ref, with w the
  * D2Q9 weights and wg = (5/9, 1/18, ..., 1/18) the rest equilibrium of
  * Eq. (53). */
