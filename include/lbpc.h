@@ -269,9 +269,9 @@ lbpc_status lbpc_batch_init_fields(lbpc_batch *b, int32_t c,
  * (>= 4). */
 lbpc_status lbpc_batch_set_tiles(lbpc_batch *b, int32_t block_width,
                                  int32_t rows);
-/* Times `steps` launches of each candidate tile shape (block width 64, 128,
- * 256 x rows 16, 24, 32, 48, 64) on the current state, keeps the fastest and
- * reports it.  The state and the phi history are left unchanged (timing
+/* Times `steps` launches of each candidate tile shape (the shape in place;
+ * block width 64, 128, 256 x rows 16, 20, 24, 32, 48, 64) on the current
+ * state, keeps the fastest and reports it.  The state and the phi history are left unchanged (timing
  * launches write phi to scratch).  Before the first step the launches read
  * the initial state in place, so tune after a step for steady-state
  * timings.  Blocks until done. */

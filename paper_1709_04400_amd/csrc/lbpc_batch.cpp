@@ -380,32 +380,36 @@ lbpc_status lbpc_batch_autotune(lbpc_batch* b, int32_t steps,
   BHIP(b, hipEventCreate(&e1), "event");
   float best = 1e30f;
   int best_bw = b->bw, best_rows = b->rows;
+  // candidates: the shape in place, then the fixed set
+  std::vector<std::array<int, 2>> cand{{b->bw, b->rows}};
+  for (int bw : CAND_BW)
+    for (int h : CAND_H) cand.push_back({bw, h});
   b->tuning = 1;
   lbpc_status st = LBPC_OK;
-  for (int bw : CAND_BW) {
-    for (int h : CAND_H) {
-      b->bw = bw;
-      b->rows = h;
-      st = build_work(b);
-      if (st == LBPC_OK) st = launch(b, b->cur);  // warm-up
-      if (st != LBPC_OK) break;
-      hipError_t e = hipEventRecord(e0, b->stream);
-      for (int s = 0; s < steps && st == LBPC_OK; ++s) st = launch(b, b->cur);
-      if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess && st == LBPC_OK)
-        st = bfail(b, LBPC_ERR_HIP, std::string("autotune timing: ") +
-                                        hipGetErrorString(e));
-      if (st != LBPC_OK) break;
-      if (ms < best) {
-        best = ms;
-        best_bw = bw;
-        best_rows = h;
-      }
-    }
+  for (size_t k = 0; k < cand.size(); ++k) {
+    bool seen = false;
+    for (size_t j = 0; j < k; ++j) seen = seen || cand[j] == cand[k];
+    if (seen) continue;
+    b->bw = cand[k][0];
+    b->rows = cand[k][1];
+    st = build_work(b);
+    if (st == LBPC_OK) st = launch(b, b->cur);  // warm-up
     if (st != LBPC_OK) break;
+    hipError_t e = hipEventRecord(e0, b->stream);
+    for (int s = 0; s < steps && st == LBPC_OK; ++s) st = launch(b, b->cur);
+    if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess && st == LBPC_OK)
+      st = bfail(b, LBPC_ERR_HIP, std::string("autotune timing: ") +
+                                      hipGetErrorString(e));
+    if (st != LBPC_OK) break;
+    if (ms < best) {
+      best = ms;
+      best_bw = cand[k][0];
+      best_rows = cand[k][1];
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
