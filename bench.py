@@ -137,8 +137,8 @@ def main():
         copy_calibration(args.calibrate_copy_mib)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU "
-              "path (see DESIGN.md for how the step would shard).",
+        print("bench.py measures one GPU only: the library has no "
+              "multi-GPU path.",
               file=sys.stderr)
         sys.exit(2)
 
