@@ -83,7 +83,7 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(
                 f"{LIB_PATH} is missing: build it with "
-                "`python -c 'import __graft_entry__ as g; g.build()'`")
+                "`python -m paper_1709_04400_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
         vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
         L.lbpc_workspace_bytes.argtypes = [ctypes.POINTER(Config),
