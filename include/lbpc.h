@@ -36,6 +36,8 @@
  * Environment, read when a handle or batch is created (scheduling only:
  * results never depend on it):
  *   LBPC_TILE_BW, LBPC_TILE_H      initial block width and rows per tile
+ *   LBPC_TILE_HE                   with LBPC_TILE_H: rows per tile of the
+ *                                  two strips holding non-periodic x sides
  *   LBPC_XCD_ORDER=0               plain tile order instead of the
  *                                  XCD-aware one
  *   LBPC_GRAPH=1, LBPC_BATCH_GRAPH=1   replay steady steps from a captured
@@ -201,11 +203,21 @@ lbpc_status lbpc_step(lbpc_handle *h, int64_t n);
 
 /* Tile shape of the step launches: threads per block (64, 128, 256 or 512;
  * the strip is at most that many columns minus 4 halo columns) and rows per
- * tile (>= 4).  Results do not depend on it.  Default: 512 for FP64 and
- * for the periodic FP32 forms, 256 otherwise; rows: 20 for the FP32 forms
- * on a lattice with a non-periodic side, otherwise the height that makes the
- * tile count just fill a whole number of waves of resident blocks. */
+ * tile (>= 4), the same for every strip.  Results do not depend on it.
+ * Default: 512 for FP64 and for the periodic FP32 forms, 256 otherwise;
+ * rows: 20 for the FP32 forms on a lattice with a non-periodic side,
+ * otherwise the height that makes the tile count just fill a whole number
+ * of waves of resident blocks, and for FP64 with non-periodic x sides
+ * shorter runs for the two strips holding those sides (their blocks take
+ * longer per row) paired with taller ones for the rest. */
 lbpc_status lbpc_set_tiles(lbpc_handle *h, int32_t block_width, int32_t rows);
+
+/* The tile shape in place: threads per block, rows per tile, and rows per
+ * tile of the two strips that hold the x sides when those are not periodic
+ * (equal to rows otherwise, and after lbpc_set_tiles).  Any pointer may be
+ * NULL. */
+lbpc_status lbpc_get_tiles(const lbpc_handle *h, int32_t *block_width,
+                           int32_t *rows, int32_t *rows_edge);
 
 /* Times `steps` launches of each candidate tile shape (the shape in place;
  * block width 64, 128, 256, 512 x rows 4 ... 64 and that width's default

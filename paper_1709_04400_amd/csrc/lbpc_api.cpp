@@ -129,17 +129,19 @@ void drop_graphs(lbpc_handle* h) {
     }
 }
 
-// tile shape of the step launches; the tile list of the non-periodic path
-// is rebuilt (and re-uploaded) at the next launch
-void set_tiles_impl(lbpc_handle* h, int bw, int rows) {
+// tile shape of the step launches (rows_edge: runs of the x-edge strips on
+// the non-periodic path); the tile list of that path is rebuilt (and
+// re-uploaded) at the next launch
+void set_tiles_impl(lbpc_handle* h, int bw, int rows, int rows_edge) {
   drop_graphs(h);
   StepParams& p = h->base;
   p.bw = bw;
   strip_shape(h->cfg.nx, bw, balanced_strips(h->cfg.precision, bw), p.nbx, p.W);
   p.H = rows;
+  p.He = rows_edge;
   p.nby = (h->cfg.ny + p.H - 1) / p.H;
   if (h->tiled) {
-    h->nwork = p.nbx * p.nby;
+    h->nwork = (int)tile_list(p).size();
     h->grid = tile_grid(h->nwork, h->cfg.precision, bw);
     h->table_valid = 0;
   }
@@ -150,11 +152,7 @@ void set_tiles_impl(lbpc_handle* h, int bw, int rows) {
 lbpc_status prepare_step(lbpc_handle* h, bool tuning) {
   if (!h->tiled) return LBPC_OK;
   if (!h->table_valid) {
-    const StepParams& b = h->base;
-    std::vector<std::array<int, 4>> tiles;
-    for (int by = 0; by < b.nby; ++by)
-      for (int bx = 0; bx < b.nbx; ++bx) tiles.push_back({0, bx, by, 0});
-    std::vector<std::array<int, 4>> work = xcd_order(tiles);
+    std::vector<std::array<int, 4>> work = xcd_order(tile_list(h->base));
     HIP_TRY(h,
             hipMemcpyAsync(at(h, h->L.work), work.data(),
                            work.size() * sizeof(work[0]),
@@ -254,18 +252,18 @@ lbpc_status lbpc_create(const lbpc_config* cfg, void* dev_workspace,
     // lbpc_autotune / lbpc_set_tiles change it
     h->tiled = !(p.perx && p.pery) || env_int("LBPC_FORCE_TILED", 0);
     h->force_gen = env_int("LBPC_FORCE_GEN", 0) != 0;
-    int bw, rows, dev = 0, cus = 256;
+    int bw, rows, rows_edge, dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
       (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
                                   dev);
     if (cus < 1) cus = 256;
     h->cus = cus;
-    default_tiles(*cfg, h->tiled != 0, cus, bw, rows);
+    default_tiles(*cfg, h->tiled != 0, cus, bw, rows, rows_edge);
     p.xcd_order = env_int("LBPC_XCD_ORDER", 1);
     // graph replay (on request: eager launches measured faster here) needs
     // a capturable (non-NULL) stream
     h->use_graph = h->stream != nullptr && env_int("LBPC_GRAPH", 0) != 0;
-    set_tiles_impl(h, bw, rows);
+    set_tiles_impl(h, bw, rows, rows_edge);
   }
   *out = h;
   return LBPC_OK;
@@ -362,7 +360,16 @@ lbpc_status lbpc_set_tiles(lbpc_handle* h, int32_t block_width,
   if (!valid_block_width(block_width))
     return fail(h, LBPC_ERR_ARG, "block width must be 64, 128, 256 or 512");
   if (rows < 4) return fail(h, LBPC_ERR_ARG, "rows must be >= 4");
-  set_tiles_impl(h, block_width, rows);
+  set_tiles_impl(h, block_width, rows, rows);
+  return LBPC_OK;
+}
+
+lbpc_status lbpc_get_tiles(const lbpc_handle* h, int32_t* block_width,
+                           int32_t* rows, int32_t* rows_edge) {
+  if (!h) return fail(nullptr, LBPC_ERR_ARG, "handle is NULL");
+  if (block_width) *block_width = h->base.bw;
+  if (rows) *rows = h->base.H;
+  if (rows_edge) *rows_edge = h->base.He;
   return LBPC_OK;
 }
 
@@ -373,26 +380,27 @@ lbpc_status lbpc_autotune(lbpc_handle* h, int32_t steps, int32_t* block_width,
   if (!h->initialised) return fail(h, LBPC_ERR_STATE, "autotune before init");
   static const int CBW[4] = {64, 128, 256, 512};
   static const int CH[7] = {4, 8, 16, 24, 32, 48, 64};
-  // candidates: the shape in place, then per block width its default height
-  // and the fixed heights
-  std::vector<std::array<int, 2>> cand{{h->base.bw, h->base.H}};
+  // candidates (block width, rows, rows of the x-edge strips): the shape in
+  // place, then per block width its default heights and the fixed heights
+  std::vector<std::array<int, 3>> cand{{h->base.bw, h->base.H, h->base.He}};
   for (int bw : CBW) {
-    cand.push_back({bw, default_rows(h->cfg, h->tiled != 0, h->cus, bw)});
-    for (int r : CH)
-      if (r <= h->cfg.ny) cand.push_back({bw, r});
+    int r, re;
+    default_rows(h->cfg, h->tiled != 0, h->cus, bw, r, re);
+    cand.push_back({bw, r, re});
+    for (int r2 : CH)
+      if (r2 <= h->cfg.ny) cand.push_back({bw, r2, r2});
   }
   hipEvent_t e0, e1;
   HIP_TRY(h, hipEventCreate(&e0), "event");
   HIP_TRY(h, hipEventCreate(&e1), "event");
   float best = 1e30f;
-  int best_bw = h->base.bw, best_rows = h->base.H;
+  std::array<int, 3> pick = cand[0];
   lbpc_status st = LBPC_OK;
   for (size_t k = 0; k < cand.size(); ++k) {
-    const int bw = cand[k][0], r = cand[k][1];
     bool seen = false;
     for (size_t j = 0; j < k; ++j) seen = seen || cand[j] == cand[k];
     if (seen) continue;
-    set_tiles_impl(h, bw, r);
+    set_tiles_impl(h, cand[k][0], cand[k][1], cand[k][2]);
     st = enqueue_step(h, true);  // warm-up (and uploads)
     if (st != LBPC_OK) break;
     hipError_t e = hipEventRecord(e0, h->stream);
@@ -406,16 +414,15 @@ lbpc_status lbpc_autotune(lbpc_handle* h, int32_t steps, int32_t* block_width,
     if (st != LBPC_OK) break;
     if (ms < best) {
       best = ms;
-      best_bw = bw;
-      best_rows = r;
+      pick = cand[k];
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  set_tiles_impl(h, best_bw, best_rows);
+  set_tiles_impl(h, pick[0], pick[1], pick[2]);
   if (st != LBPC_OK) return st;
-  if (block_width) *block_width = best_bw;
-  if (rows) *rows = best_rows;
+  if (block_width) *block_width = pick[0];
+  if (rows) *rows = pick[1];
   if (ms_per_step) *ms_per_step = best / steps;
   return LBPC_OK;
 }

@@ -190,6 +190,7 @@ StepParams case_params(lbpc_batch* b, int c, int par) {
   p.bw = b->bw;
   strip_shape(p.nx, b->bw, true, p.nbx, p.W);
   p.H = b->rows;
+  p.He = b->rows;  // batches run uniform row runs
   p.nby = (p.ny + p.H - 1) / p.H;
   p.xcd_order = 0;
   return p;

@@ -23,6 +23,8 @@ struct StepParams {
   int perx, pery;          // 1 if that axis is periodic
   int bc[4];               // side kinds x-, x+, y-, y+
   int W, H;                // interior columns / rows per block
+  int He;                  // rows per block of the x-edge strips when the x
+                           // sides are not periodic (tile-list kernel)
   int nbx, nby;            // blocks along x and y
   int bw;                  // threads per block (strip width incl. halo)
   int xcd_order;           // 1: blocks of one XCD take x-adjacent strips

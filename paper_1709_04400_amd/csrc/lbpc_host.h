@@ -4,6 +4,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -339,37 +340,106 @@ inline int fill_rows(int ny, int nbx, long long slots) {
   return best_rows;
 }
 
-// Default rows per tile of a single lattice for block width bw.  Periodic
-// lattices and FP64: the wave-filling height of fill_rows for the device's
-// CUs.  The FP32 forms on non-periodic lattices (the boundary-capable tile
-// kernel, 256-thread blocks, three per CU) run fastest with short tiles,
-// against the model: on a 4096^2 lattice walled on all four sides, 20 rows
-// against the wave-filling 92 gave FP32 27.3k against 24.8k MLUPS, FP32
-// deviations 25.4k against 23.7k, FP16 deviations 31.4k against 30.3k, with
-// 16 and 24 rows within 3 % of 20.  (FP64 there: 37 and 147 rows within 1 %.)
-inline int default_rows(const lbpc_config& c, bool tiled, int cus, int bw) {
-  if (tiled && c.precision != LBPC_FP64) return c.ny < 20 ? c.ny : 20;
-  int nbx, W;
-  strip_shape(c.nx, bw, balanced_strips(c.precision, bw), nbx, W);
-  return fill_rows(c.ny, nbx, (long long)cus * blocks_per_cu(c.precision, bw));
+// Strips holding a non-periodic x side; on the tile-list path they may run
+// shorter row runs (He rows) than the others (H rows).
+inline bool edge_strip(const StepParams& p, int bx) {
+  return !p.perx && (bx == 0 || bx == p.nbx - 1);
 }
 
-// Default tile shape of a single lattice (LBPC_TILE_BW and LBPC_TILE_H
-// override it; lbpc_autotune and lbpc_set_tiles change it later).
-// 512-thread blocks (8 waves, one block per CU at 2 waves per SIMD) read
-// half the halo columns of 256-thread strips: at 4096^2 FP64 +3.8 % (+3.6 %
-// with walls), periodic FP32 +5 %.  The FP32 forms on non-periodic lattices
-// (the heavier boundary-capable kernel, -11 %) and the FP16-deviation form
-// (bound by instruction issue, -16 %) need their 3 waves per SIMD and keep
-// 256.
+// The tiles of one lattice as (0, bx, by, 0), row of runs by row of runs.
+inline std::vector<std::array<int, 4>> tile_list(const StepParams& p) {
+  const int ni = (p.ny + p.H - 1) / p.H, ne = (p.ny + p.He - 1) / p.He;
+  const int nmax = ni > ne ? ni : ne;
+  std::vector<std::array<int, 4>> t;
+  for (int by = 0; by < nmax; ++by)
+    for (int bx = 0; bx < p.nbx; ++bx)
+      if (by < (edge_strip(p, bx) ? ne : ni)) t.push_back({0, bx, by, 0});
+  return t;
+}
+
+// Row time of an x-edge strip over an interior one for the FP64
+// boundary-capable kernel: its edge waves run the side rules in every row
+// and each block waits for its slowest wave at the row barrier (4096^2,
+// 512 x 147 tiles in one wave: walls on the x sides 1.184 ms per step
+// against 1.097 ms for the same kernel on periodic sides).
+constexpr double EDGE_ROW_COST = 1.08;
+
+// Interior and edge-strip heights for nbx strips of which ne hold an x side:
+// the waves x (the slower of an interior tile's rows + 4 and an edge tile's
+// EDGE_ROW_COST x (rows + 4)) minimised over H >= 16 and He <= H.  A height
+// He below (H + 4) / EDGE_ROW_COST - 4 only adds tiles, so the search starts
+// there.  4096^2: H = 147, He = 137, 7 x 28 + 2 x 30 = 256 tiles in one wave.
+inline void fill_rows_edges(int ny, int nbx, int ne, long long slots,
+                            int& H, int& He) {
+  const int lo = ny < 16 ? ny : 16;
+  double best = -1.0;
+  H = He = lo;
+  for (int h = lo; h <= ny; ++h) {
+    int e0 = (int)std::ceil((h + 4) / EDGE_ROW_COST - 4.0);
+    if (e0 < lo) e0 = lo;
+    if (ne == nbx) e0 = h;  // no interior strips: one height
+    for (int e = e0; e <= h; ++e) {
+      const long long tiles = (long long)(nbx - ne) * ((ny + h - 1) / h) +
+                              (long long)ne * ((ny + e - 1) / e);
+      const long long waves = (tiles + slots - 1) / slots;
+      const double ti = nbx > ne ? h + 4.0 : 0.0;
+      const double te = EDGE_ROW_COST * (e + 4.0);
+      const double cost = (double)waves * (ti > te ? ti : te);
+      if (best < 0.0 || cost < best - 1e-9) {
+        best = cost;
+        H = h;
+        He = e;
+      }
+    }
+  }
+}
+
+// Default rows per tile of a single lattice for block width bw (rows_edge:
+// the x-edge strips' runs).  Periodic lattices and FP64: the wave-filling
+// height of fill_rows for the device's CUs, and for FP64 with non-periodic
+// x sides the pair of fill_rows_edges.  The FP32 forms on non-periodic
+// lattices (the boundary-capable tile kernel, 256-thread blocks, three per
+// CU) run fastest with short tiles, against the model: on a 4096^2 lattice
+// walled on all four sides, 20 rows against the wave-filling 92 gave FP32
+// 27.3k against 24.8k MLUPS, FP32 deviations 25.4k against 23.7k, FP16
+// deviations 31.4k against 30.3k, with 16 and 24 rows within 3 % of 20.
+inline void default_rows(const lbpc_config& c, bool tiled, int cus, int bw,
+                         int& rows, int& rows_edge) {
+  if (tiled && c.precision != LBPC_FP64) {
+    rows = rows_edge = c.ny < 20 ? c.ny : 20;
+    return;
+  }
+  int nbx, W;
+  strip_shape(c.nx, bw, balanced_strips(c.precision, bw), nbx, W);
+  const long long slots = (long long)cus * blocks_per_cu(c.precision, bw);
+  if (tiled && c.bc[0] != LBPC_BC_PERIODIC) {
+    fill_rows_edges(c.ny, nbx, nbx == 1 ? 1 : 2, slots, rows, rows_edge);
+    return;
+  }
+  rows = rows_edge = fill_rows(c.ny, nbx, slots);
+}
+
+// Default tile shape of a single lattice (LBPC_TILE_BW, LBPC_TILE_H and,
+// with LBPC_TILE_H, LBPC_TILE_HE override it; lbpc_autotune and
+// lbpc_set_tiles change it later).  512-thread blocks (8 waves, one
+// block per CU at 2 waves per SIMD) read half the halo columns of
+// 256-thread strips: at 4096^2 FP64 +3.8 % (+3.6 % with walls), periodic
+// FP32 +5 %.  The FP32 forms on non-periodic lattices (the heavier
+// boundary-capable kernel, -11 %) and the FP16-deviation form (bound by
+// instruction issue, -16 %) need their 3 waves per SIMD and keep 256.
 inline void default_tiles(const lbpc_config& c, bool tiled, int cus, int& bw,
-                          int& rows) {
+                          int& rows, int& rows_edge) {
   const bool wide = c.precision == LBPC_FP64 ||
                     (c.precision != LBPC_FP16_SHIFTED && !tiled);
   bw = env_int("LBPC_TILE_BW", wide ? 512 : 256);
   if (!valid_block_width(bw)) bw = 256;
   rows = env_int("LBPC_TILE_H", 0);
-  if (rows <= 0) rows = default_rows(c, tiled, cus, bw);
+  if (rows > 0) {
+    rows_edge = env_int("LBPC_TILE_HE", rows);
+    if (rows_edge < 4) rows_edge = rows;
+  } else {
+    default_rows(c, tiled, cus, bw, rows, rows_edge);
+  }
 }
 
 }  // namespace lbpc_host

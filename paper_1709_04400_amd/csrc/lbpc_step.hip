@@ -79,7 +79,13 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
   const int nx = p.nx, ny = p.ny;
   const long long N = p.N;
   const int X0 = bx * p.W, X1 = min(X0 + p.W, nx);
-  const int Y0 = by * p.H, Y1 = min(Y0 + p.H, ny);
+  // the strips holding a non-periodic x side may run shorter row runs: their
+  // edge waves do more work per row
+  int Hr = p.H;
+  if constexpr (GEN) {
+    if (!p.perx && (bx == 0 || bx == p.nbx - 1)) Hr = p.He;
+  }
+  const int Y0 = by * Hr, Y1 = min(Y0 + Hr, ny);
   const int c = X0 - HALO + t;  // unwrapped column of this thread
 
   const S* __restrict__ fin = static_cast<const S*>(p.fin);

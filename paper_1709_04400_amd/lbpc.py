@@ -25,7 +25,7 @@ EXPORTS = (
     "lbpc_workspace_bytes", "lbpc_create", "lbpc_init_fields", "lbpc_step",
     "lbpc_get_rho_u_T", "lbpc_get_diag", "lbpc_state_bytes",
     "lbpc_save_state", "lbpc_load_state", "lbpc_destroy", "lbpc_last_error",
-    "lbpc_set_tiles", "lbpc_autotune", "lbpc_batch_workspace_bytes", "lbpc_batch_create",
+    "lbpc_set_tiles", "lbpc_get_tiles", "lbpc_autotune", "lbpc_batch_workspace_bytes", "lbpc_batch_create",
     "lbpc_batch_init_fields", "lbpc_batch_set_tiles", "lbpc_batch_autotune",
     "lbpc_batch_step", "lbpc_batch_get_rho_u_T", "lbpc_batch_get_diag",
     "lbpc_batch_nodes", "lbpc_batch_destroy", "lbpc_batch_last_error",
@@ -103,6 +103,8 @@ def lib():
         L.lbpc_last_error.restype = ctypes.c_char_p
         i32, i64p = ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)
         L.lbpc_set_tiles.argtypes = [vp, i32, i32]
+        L.lbpc_get_tiles.argtypes = [vp, ctypes.POINTER(i32),
+                                     ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.lbpc_autotune.argtypes = [vp, i32, ctypes.POINTER(i32),
                                     ctypes.POINTER(i32), dp]
         L.lbpc_batch_workspace_bytes.argtypes = [
@@ -210,6 +212,14 @@ def lbpc_load_state(h, buf: np.ndarray):
                                  buf.nbytes), h)
 
 
+def lbpc_get_tiles(h) -> dict:
+    bw, rows, re = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().lbpc_get_tiles(h, ctypes.byref(bw), ctypes.byref(rows),
+                                ctypes.byref(re)), h)
+    return {"block_width": bw.value, "rows": rows.value,
+            "rows_edge": re.value}
+
+
 def lbpc_destroy(h):
     lib().lbpc_destroy(h)
 
@@ -273,6 +283,9 @@ class Simulation:
     def set_tiles(self, block_width, rows):
         _check(lib().lbpc_set_tiles(self.h, int(block_width), int(rows)),
                self.h)
+
+    def tiles(self) -> dict:
+        return lbpc_get_tiles(self.h)
 
     def autotune(self, steps=3):
         bw, rows = ctypes.c_int32(), ctypes.c_int32()

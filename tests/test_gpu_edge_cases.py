@@ -148,3 +148,63 @@ def test_batch_mixing_smallest_and_larger_lattices():
         print(f"[edge] batch lattice {k}", flush=True)
         _check(b.rho_u_T(k), o.rho_u_T())
     b.close()
+
+
+def _with_env(env, fn):
+    import os
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update({k: str(v) for k, v in env.items()})
+    try:
+        return fn()
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+@pytest.mark.parametrize("prec", [I.FP64, I.FP32])
+def test_shorter_runs_in_the_x_edge_strips(prec):
+    """Strips holding walls on the x sides with their own run height (13
+    rows against 24 elsewhere, 128-thread blocks: 3 strips, so runs of
+    different heights meet along both strip boundaries) on a walled
+    boiling cut with a hot spot: the same result as the oracle."""
+    cfg, fl = _cut(300, 200, "walls")
+    cfg.update(hot_x0=140, hot_x1=160, T_hot=1.1 * I.T_SAT,
+               lambda_mode=I.LAMBDA_RHO_CV_CHI, chi=I.CHI_BUBBLE,
+               precision=prec)
+    o = O.Oracle(dict(cfg, precision=I.FP64))
+    o.init_fields(**fl)
+    o.step(60)
+    g = _with_env({"LBPC_TILE_BW": 128, "LBPC_TILE_H": 24,
+                   "LBPC_TILE_HE": 13}, lambda: _lb().Simulation(cfg))
+    assert g.tiles() == {"block_width": 128, "rows": 24, "rows_edge": 13}
+    g.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
+    g.step(60)
+    if prec == I.FP64:
+        _check(g.rho_u_T(), o.rho_u_T())
+    else:
+        e = _errors(g.rho_u_T(), o.rho_u_T())
+        assert e["rho"] < SHORT[prec] and e["T"] < SHORT[prec], e
+    g.close()
+
+
+def test_default_edge_runs_on_a_wide_walled_lattice():
+    """1530 x 1100 FP64 walled on all sides: on a 256-CU device the default
+    gives the two x-edge strips (of four) shorter runs than the others;
+    five steps agree with the oracle over the whole lattice."""
+    cfg, fl = _cut(1530, 1100, "walls")
+    g = _lb().Simulation(cfg)
+    t = g.tiles()
+    print(f"\n[edge] default tiles {t}", flush=True)
+    g.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
+    g.step(5)
+    o = O.Oracle(cfg)
+    o.init_fields(**fl)
+    o.step(5)
+    _check(g.rho_u_T(), o.rho_u_T())
+    g.close()
+    import torch
+    if torch.cuda.get_device_properties(0).multi_processor_count == 256:
+        assert t["rows_edge"] < t["rows"], t

@@ -102,6 +102,38 @@ def test_create_checks_workspace_and_flags():
     lb.lbpc_destroy(h)
 
 
+def test_default_tile_shapes():
+    """Default tiles on a device of 256 CUs (the count assumed where none is
+    visible): 4096^2 FP64 fills one wave of 256 one-block-per-CU slots with
+    9 strips of 28 runs of 147 rows; with walls on the x sides the two edge
+    strips take 30 runs of 137 rows and the rest 28 of 147 (256 tiles); the
+    FP32 forms on a walled lattice take 20 rows; lbpc_set_tiles makes every
+    strip's runs alike."""
+    lb = _lbpc()
+    W, P = I.BC_WALL, I.BC_PERIODIC
+
+    def shape(bc, prec=I.FP64):
+        cfg = I.base_config(4096, 4096, bc=bc, precision=prec)
+        h = lb.lbpc_create(cfg, 4096, lb.lbpc_workspace_bytes(cfg), 0)
+        t = lb.lbpc_get_tiles(h)
+        return h, (t["block_width"], t["rows"], t["rows_edge"])
+
+    for bc, want in (([P] * 4, (512, 147, 147)), ([W] * 4, (512, 147, 137)),
+                     ([W, W, P, P], (512, 147, 137)),
+                     ([P, P, W, W], (512, 147, 147))):
+        h, got = shape(bc)
+        lb.lbpc_destroy(h)
+        assert got == want, (bc, got)
+    h, got = shape([W] * 4, I.FP32)
+    lb.lbpc_destroy(h)
+    assert got == (256, 20, 20)
+    h, _ = shape([W] * 4)
+    lb._check(lb.lib().lbpc_set_tiles(h, 256, 24), h)
+    t = lb.lbpc_get_tiles(h)
+    lb.lbpc_destroy(h)
+    assert (t["block_width"], t["rows"], t["rows_edge"]) == (256, 24, 24)
+
+
 def test_batch_workspace_bytes():
     lb = _lbpc()
     cases = I.batch_cases(count=8, seed=3)
