@@ -579,9 +579,16 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
   }
 }
 
+// Waves per SIMD a block shape can reach: a 512-thread block (8 waves) with
+// its 100-104 KiB of LDS runs one per CU, i.e. 2 waves per SIMD, whatever
+// the form's register budget would allow.
+template <int P, int BLOCK> struct BlockOcc {
+  static constexpr int waves = BLOCK == 512 ? 2 : StepOcc<P>::waves;
+};
+
 template <int P, bool GEN, int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((
-    amdgpu_waves_per_eu(StepOcc<P>::waves, StepOcc<P>::waves))) void
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(
+    BlockOcc<P, BLOCK>::waves, BlockOcc<P, BLOCK>::waves))) void
 k_step(StepParams p) {
   int bx, by;
   block_tile(p, bx, by);
@@ -598,8 +605,8 @@ struct WorkItem {
 };
 
 template <int P, int BLOCK, bool GEN>
-__global__ __launch_bounds__(BLOCK) __attribute__((
-    amdgpu_waves_per_eu(StepOcc<P>::waves, StepOcc<P>::waves))) void
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(
+    BlockOcc<P, BLOCK>::waves, BlockOcc<P, BLOCK>::waves))) void
 k_step_batch(const StepParams* __restrict__ table,
              const WorkItem* __restrict__ work, int nwork, int parity) {
   for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
