@@ -214,8 +214,8 @@ lbpc_status lbpc_set_tiles(lbpc_handle *h, int32_t block_width, int32_t rows);
 
 /* The tile shape in place: threads per block, rows per tile, and rows per
  * tile of the two strips that hold the x sides when those are not periodic
- * (equal to rows otherwise, and after lbpc_set_tiles).  Any pointer may be
- * NULL. */
+ * (equal to rows otherwise, and after lbpc_set_tiles).  Any output pointer
+ * may be NULL; LBPC_ERR_ARG if h is NULL.  Host only: no device work. */
 lbpc_status lbpc_get_tiles(const lbpc_handle *h, int32_t *block_width,
                            int32_t *rows, int32_t *rows_edge);
 
