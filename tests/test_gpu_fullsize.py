@@ -132,3 +132,60 @@ def test_full_sweep_batch_sampled_lattices(prec):
     b.close()
     print(f"\n[fullsize] batch prec={prec} lattices {pick} worst {worst:.2e}",
           flush=True)
+
+
+def _cut_window(a, x0, y0):
+    return a[..., y0:y0 + WIN, x0:x0 + WIN]
+
+
+def test_walled_4096_fp64_edge_runs_in_windows():
+    """The 4096 x 4096 spinodal walled on all four sides, FP64, default tiles
+    (on a 256-CU device the two x-edge strips run 137-row runs and the others
+    147-row runs, all in one wave).  After 20 steps one more GPU step is
+    compared in windows: at each wall (the oracle window keeps that wall; a
+    cut side gets a wall or the periodic pair and is excluded with the
+    dependence margin), at a corner, and where an edge strip's run boundary
+    (y = 1918) and an interior strip's (y = 1911) meet across a strip
+    boundary (x = 456)."""
+    from paper_1709_04400_amd import lbpc
+    W_, P_ = I.BC_WALL, I.BC_PERIODIC
+    cfg, fl = I.spinodal(N, precision=I.FP64)
+    cfg["bc"] = [W_] * 4
+    g = lbpc.Simulation(cfg)
+    print(f"\n[fullsize] walled FP64 tiles {g.tiles()}", flush=True)
+    g.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
+    del fl
+    g.step(20)
+    s0 = g.save_state()
+    g.step(1)
+    s1 = g.save_state()
+    g.close()
+    f0, g0, p0, valid, rho_ave, step = _split(s0)
+    f1, g1, _, _, _, _ = _split(s1)
+    # (x0, y0) of each window; which window sides are the lattice's walls
+    wins = [(0, 399), (N - WIN, 1200), (2000, 0), (2000, N - WIN), (0, 0),
+            (444, 1903)]
+    worst = 0.0
+    for x0, y0 in wins:
+        real = [x0 == 0, x0 + WIN == N, y0 == 0, y0 + WIN == N]
+        bx = W_ if real[0] or real[1] else P_
+        by = W_ if real[2] or real[3] else P_
+        ocfg = dict(cfg, nx=WIN, ny=WIN, bc=[bx, bx, by, by])
+        o = O.Oracle(ocfg)
+        o.set_state({"f": _cut_window(f0, x0, y0),
+                     "g": _cut_window(g0, x0, y0),
+                     "phi_prev": _cut_window(p0, x0, y0),
+                     "phi_valid": valid, "rho_ave": rho_ave, "step": step})
+        o.step(1)
+        st = o.get_state()
+        xs = slice(0 if real[0] else MARGIN, WIN if real[1] else WIN - MARGIN)
+        ys = slice(0 if real[2] else MARGIN, WIN if real[3] else WIN - MARGIN)
+        fo = st["f"].reshape(9, WIN, WIN)[:, ys, xs]
+        go = st["g"].reshape(9, WIN, WIN)[:, ys, xs]
+        fg = _cut_window(f1, x0, y0)[:, ys, xs]
+        gg = _cut_window(g1, x0, y0)[:, ys, xs]
+        e_f = np.abs(fg - fo).max() / np.abs(fo).max()
+        e_g = np.abs(gg - go).max() / np.abs(go).max()
+        worst = max(worst, e_f, e_g)
+        assert e_f < TOL[I.FP64] and e_g < TOL[I.FP64], (x0, y0, e_f, e_g)
+    print(f"[fullsize] walled FP64 worst window error {worst:.2e}", flush=True)
