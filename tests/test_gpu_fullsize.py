@@ -189,3 +189,48 @@ def test_walled_4096_fp64_edge_runs_in_windows():
         worst = max(worst, e_f, e_g)
         assert e_f < TOL[I.FP64] and e_g < TOL[I.FP64], (x0, y0, e_f, e_g)
     print(f"[fullsize] walled FP64 worst window error {worst:.2e}", flush=True)
+
+
+def test_16384_fp64_offsets_beyond_2_31_elements():
+    """The largest lattice here: 16384 x 16384 FP64 (2.7e8 nodes, 86 GiB of
+    workspace), whose f and g buffers hold 2.4e9 elements, so rows above
+    y = 14563 sit at element offsets past 2^31.  Two GPU steps from the
+    seeded spinodal state; rho, u and T then match, in windows, the oracle
+    stepping the same initial state cut out with a margin of 8 (two steps
+    reach 3 nodes each, the readback of v one more).  Windows in the top
+    rows, at the periodic corner and in the middle."""
+    import torch
+    from paper_1709_04400_amd import lbpc
+    n, win, margin = 16384, 32, 8
+    cfg, fl = I.spinodal(n, precision=I.FP64)
+    need = lbpc.lbpc_workspace_bytes(cfg)
+    free, _ = torch.cuda.mem_get_info()
+    if free < need + (4 << 30):
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of device memory")
+    g = lbpc.Simulation(cfg)
+    g.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
+    g.step(2)
+    out = g.rho_u_T()
+    g.close()
+    del g
+    worst = 0.0
+    for cx, cy in [(100, n - 5), (n // 2, n - 700), (0, 0), (n - 1, n - 1),
+                   (8000, 8000)]:
+        ys = (np.arange(cy - win // 2, cy + win // 2)) % n
+        xs = (np.arange(cx - win // 2, cx + win // 2)) % n
+        cut = {k: np.ascontiguousarray(v[ys[:, None], xs[None, :]])
+               for k, v in fl.items()}
+        o = O.Oracle(dict(cfg, nx=win, ny=win))
+        o.init_fields(**cut)
+        o.step(2)
+        ref = o.rho_u_T()
+        inner = slice(margin, win - margin)
+        for k, (a, b) in enumerate(zip(out, ref)):
+            ga = a[ys[:, None], xs[None, :]][inner, inner]
+            rb = b[inner, inner]
+            scale = np.abs(rb).max() if k in (1, 2) else np.abs(rb).min()
+            e = np.abs(ga - rb).max() / scale
+            worst = max(worst, e)
+            assert e < 1e-12, (cx, cy, k, e)
+    print(f"\n[fullsize] 16384^2 FP64 worst window error {worst:.2e}",
+          flush=True)
