@@ -409,7 +409,23 @@ __device__ __forceinline__ void cook_g(const StepParams& p, const Shift<P>& sh,
   }
   if (GEN && !p.fresh) {
     const EdgeSides e(p, x, y, true);
-    if (__builtin_amdgcn_ballot_w64(e.any()) != 0) {
+    const bool edge = __builtin_amdgcn_ballot_w64(e.any()) != 0;
+    // FP32 arithmetic: a row away from the y sides takes only the directions
+    // arriving across an x side, at that side's temperature (not FP64, as in
+    // stage C of the step)
+    bool xonly = false;
+    if constexpr (sizeof(C) == 4) xonly = !(e.o2 || e.o3);
+    if (edge && xonly) {
+      const bool w0 = p.bc[0] == BC_WALL, w1 = p.bc[1] == BC_WALL;
+#pragma unroll
+      for (int a = 1; a < Q; ++a) {
+        if (EXs[a] == 0) continue;
+        const bool ox = EXs[a] > 0 ? e.o0 : e.o1;
+        const bool wall = ox && (EXs[a] > 0 ? w0 : w1);
+        const C wT = C(w_rest(p, a)) * C(p.T_bc[EXs[a] > 0 ? 0 : 1]);
+        g[a] = wall ? C(2) * wT - g[a] : (ox ? wT : g[a]);
+      }
+    } else if (edge) {
       const int xm = wrap_or_clamp(x - 1, p.nx, p.perx);
       const int xp = wrap_or_clamp(x + 1, p.nx, p.perx);
 #pragma unroll
