@@ -395,24 +395,24 @@ inline void fill_rows_edges(int ny, int nbx, int ne, long long slots,
 }
 
 // Default rows per tile of a single lattice for block width bw (rows_edge:
-// the x-edge strips' runs).  Periodic lattices and FP64: the wave-filling
-// height of fill_rows for the device's CUs, and for FP64 with non-periodic
-// x sides the pair of fill_rows_edges.  The FP32 forms on non-periodic
-// lattices (the boundary-capable tile kernel, 256-thread blocks, three per
-// CU) run fastest with short tiles, against the model: on a 4096^2 lattice
-// walled on all four sides, 20 rows against the wave-filling 92 gave FP32
-// 27.3k against 24.8k MLUPS, FP32 deviations 25.4k against 23.7k, FP16
-// deviations 31.4k against 30.3k, with 16 and 24 rows within 3 % of 20.
+// the x-edge strips' runs).  The wave-filling height of fill_rows for the
+// device's CUs, and for FP64 with non-periodic x sides the pair of
+// fill_rows_edges.  One exception: plain FP32 storage on a non-periodic
+// lattice (the boundary-capable tile kernel, 256-thread blocks, three per
+// CU) runs short tiles best.  On a 4096^2 lattice walled on all four sides:
+// FP32 28.4k MLUPS at 20 rows against 27.8k at the wave-filling 92 (16 rows
+// 28.7k, 46 rows 28.1k); FP32 deviations 27.9k at 92 against 27.2k at 20;
+// FP16 deviations 37.2k at 92 against 34.9k at 20.
 inline void default_rows(const lbpc_config& c, bool tiled, int cus, int bw,
                          int& rows, int& rows_edge) {
-  if (tiled && c.precision != LBPC_FP64) {
+  if (tiled && c.precision == LBPC_FP32) {
     rows = rows_edge = c.ny < 20 ? c.ny : 20;
     return;
   }
   int nbx, W;
   strip_shape(c.nx, bw, balanced_strips(c.precision, bw), nbx, W);
   const long long slots = (long long)cus * blocks_per_cu(c.precision, bw);
-  if (tiled && c.bc[0] != LBPC_BC_PERIODIC) {
+  if (tiled && c.precision == LBPC_FP64 && c.bc[0] != LBPC_BC_PERIODIC) {
     fill_rows_edges(c.ny, nbx, nbx == 1 ? 1 : 2, slots, rows, rows_edge);
     return;
   }

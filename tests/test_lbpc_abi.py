@@ -106,9 +106,9 @@ def test_default_tile_shapes():
     """Default tiles on a device of 256 CUs (the count assumed where none is
     visible): 4096^2 FP64 fills one wave of 256 one-block-per-CU slots with
     9 strips of 28 runs of 147 rows; with walls on the x sides the two edge
-    strips take 30 runs of 137 rows and the rest 28 of 147 (256 tiles); the
-    FP32 forms on a walled lattice take 20 rows; lbpc_set_tiles makes every
-    strip's runs alike."""
+    strips take 30 runs of 137 rows and the rest 28 of 147 (256 tiles); plain
+    FP32 on a walled lattice takes 20 rows, FP16 deviations the wave-filling
+    92; lbpc_set_tiles makes every strip's runs alike."""
     lb = _lbpc()
     W, P = I.BC_WALL, I.BC_PERIODIC
 
@@ -127,6 +127,11 @@ def test_default_tile_shapes():
     h, got = shape([W] * 4, I.FP32)
     lb.lbpc_destroy(h)
     assert got == (256, 20, 20)
+    # FP16 deviations: 17 strips of 252 columns x 45 runs of 92 rows = 765
+    # tiles in one wave of 3 x 256 slots
+    h, got = shape([W] * 4, I.FP16_SHIFTED)
+    lb.lbpc_destroy(h)
+    assert got == (256, 92, 92)
     h, _ = shape([W] * 4)
     lb._check(lb.lib().lbpc_set_tiles(h, 256, 24), h)
     t = lb.lbpc_get_tiles(h)
