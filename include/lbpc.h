@@ -208,9 +208,7 @@ lbpc_status lbpc_step(lbpc_handle *h, int64_t n);
  * Default: 512 for FP64 and for the periodic FP32 forms, 256 otherwise;
  * rows: 20 for plain FP32 on a lattice with a non-periodic side, otherwise
  * the height that makes the tile count just fill a whole number of waves
- * of resident blocks, and for FP64 with non-periodic x sides
- * shorter runs for the two strips holding those sides (their blocks take
- * longer per row) paired with taller ones for the rest. */
+ * of resident blocks. */
 lbpc_status lbpc_set_tiles(lbpc_handle *h, int32_t block_width, int32_t rows);
 
 /* The tile shape in place: threads per block, rows per tile, and rows per

@@ -410,11 +410,9 @@ __device__ __forceinline__ void cook_g(const StepParams& p, const Shift<P>& sh,
   if (GEN && !p.fresh) {
     const EdgeSides e(p, x, y, true);
     const bool edge = __builtin_amdgcn_ballot_w64(e.any()) != 0;
-    // FP32 arithmetic: a row away from the y sides takes only the directions
-    // arriving across an x side, at that side's temperature (not FP64, as in
-    // stage C of the step)
-    bool xonly = false;
-    if constexpr (sizeof(C) == 4) xonly = !(e.o2 || e.o3);
+    // a row away from the y sides takes only the directions arriving across
+    // an x side, at that side's temperature
+    const bool xonly = !(e.o2 || e.o3);
     if (edge && xonly) {
       const bool w0 = p.bc[0] == BC_WALL, w1 = p.bc[1] == BC_WALL;
 #pragma unroll

@@ -357,47 +357,10 @@ inline std::vector<std::array<int, 4>> tile_list(const StepParams& p) {
   return t;
 }
 
-// Row time of an x-edge strip over an interior one for the FP64
-// boundary-capable kernel: its edge waves run the side rules in every row
-// and each block waits for its slowest wave at the row barrier (4096^2,
-// 512 x 147 tiles in one wave: walls on the x sides 1.184 ms per step
-// against 1.097 ms for the same kernel on periodic sides).
-constexpr double EDGE_ROW_COST = 1.08;
-
-// Interior and edge-strip heights for nbx strips of which ne hold an x side:
-// the waves x (the slower of an interior tile's rows + 4 and an edge tile's
-// EDGE_ROW_COST x (rows + 4)) minimised over H >= 16 and He <= H.  A height
-// He below (H + 4) / EDGE_ROW_COST - 4 only adds tiles, so the search starts
-// there.  4096^2: H = 147, He = 137, 7 x 28 + 2 x 30 = 256 tiles in one wave.
-inline void fill_rows_edges(int ny, int nbx, int ne, long long slots,
-                            int& H, int& He) {
-  const int lo = ny < 16 ? ny : 16;
-  double best = -1.0;
-  H = He = lo;
-  for (int h = lo; h <= ny; ++h) {
-    int e0 = (int)std::ceil((h + 4) / EDGE_ROW_COST - 4.0);
-    if (e0 < lo) e0 = lo;
-    if (ne == nbx) e0 = h;  // no interior strips: one height
-    for (int e = e0; e <= h; ++e) {
-      const long long tiles = (long long)(nbx - ne) * ((ny + h - 1) / h) +
-                              (long long)ne * ((ny + e - 1) / e);
-      const long long waves = (tiles + slots - 1) / slots;
-      const double ti = nbx > ne ? h + 4.0 : 0.0;
-      const double te = EDGE_ROW_COST * (e + 4.0);
-      const double cost = (double)waves * (ti > te ? ti : te);
-      if (best < 0.0 || cost < best - 1e-9) {
-        best = cost;
-        H = h;
-        He = e;
-      }
-    }
-  }
-}
-
 // Default rows per tile of a single lattice for block width bw (rows_edge:
-// the x-edge strips' runs).  The wave-filling height of fill_rows for the
-// device's CUs, and for FP64 with non-periodic x sides the pair of
-// fill_rows_edges.  One exception: plain FP32 storage on a non-periodic
+// the x-edge strips' runs, the same height by default).  The wave-filling
+// height of fill_rows for the device's CUs.  One exception: plain FP32
+// storage on a non-periodic
 // lattice (the boundary-capable tile kernel, 256-thread blocks, three per
 // CU) runs short tiles best.  On a 4096^2 lattice walled on all four sides:
 // FP32 28.4k MLUPS at 20 rows against 27.8k at the wave-filling 92 (16 rows
@@ -412,10 +375,6 @@ inline void default_rows(const lbpc_config& c, bool tiled, int cus, int bw,
   int nbx, W;
   strip_shape(c.nx, bw, balanced_strips(c.precision, bw), nbx, W);
   const long long slots = (long long)cus * blocks_per_cu(c.precision, bw);
-  if (tiled && c.precision == LBPC_FP64 && c.bc[0] != LBPC_BC_PERIODIC) {
-    fill_rows_edges(c.ny, nbx, nbx == 1 ? 1 : 2, slots, rows, rows_edge);
-    return;
-  }
   rows = rows_edge = fill_rows(c.ny, nbx, slots);
 }
 

@@ -139,20 +139,30 @@ def _cut_window(a, x0, y0):
 
 
 def test_walled_4096_fp64_edge_runs_in_windows():
-    """The 4096 x 4096 spinodal walled on all four sides, FP64, default tiles
-    (on a 256-CU device the two x-edge strips run 137-row runs and the others
-    147-row runs, all in one wave).  After 20 steps one more GPU step is
-    compared in windows: at each wall (the oracle window keeps that wall; a
-    cut side gets a wall or the periodic pair and is excluded with the
-    dependence margin), at a corner, and where an edge strip's run boundary
-    (y = 1918) and an interior strip's (y = 1911) meet across a strip
-    boundary (x = 456)."""
+    """The 4096 x 4096 spinodal walled on all four sides, FP64, with the two
+    x-edge strips on 137-row runs and the others on 147-row runs (all in one
+    wave).  After 20 steps one more GPU step is compared in windows: at each
+    wall (the oracle window keeps that wall; a cut side gets a wall or the
+    periodic pair and is excluded with the dependence margin), at a corner,
+    and where an edge strip's run boundary (y = 1918) and an interior
+    strip's (y = 1911) meet across a strip boundary (x = 456)."""
     from paper_1709_04400_amd import lbpc
     W_, P_ = I.BC_WALL, I.BC_PERIODIC
+    import os
     cfg, fl = I.spinodal(N, precision=I.FP64)
     cfg["bc"] = [W_] * 4
-    g = lbpc.Simulation(cfg)
-    print(f"\n[fullsize] walled FP64 tiles {g.tiles()}", flush=True)
+    env = {"LBPC_TILE_BW": "512", "LBPC_TILE_H": "147", "LBPC_TILE_HE": "137"}
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        g = lbpc.Simulation(cfg)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    assert g.tiles() == {"block_width": 512, "rows": 147, "rows_edge": 137}
     g.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
     del fl
     g.step(20)

@@ -105,8 +105,7 @@ def test_create_checks_workspace_and_flags():
 def test_default_tile_shapes():
     """Default tiles on a device of 256 CUs (the count assumed where none is
     visible): 4096^2 FP64 fills one wave of 256 one-block-per-CU slots with
-    9 strips of 28 runs of 147 rows; with walls on the x sides the two edge
-    strips take 30 runs of 137 rows and the rest 28 of 147 (256 tiles); plain
+    9 strips of 28 runs of 147 rows, with walls on any side too; plain
     FP32 on a walled lattice takes 20 rows, FP16 deviations the wave-filling
     92; lbpc_set_tiles makes every strip's runs alike."""
     lb = _lbpc()
@@ -118,8 +117,8 @@ def test_default_tile_shapes():
         t = lb.lbpc_get_tiles(h)
         return h, (t["block_width"], t["rows"], t["rows_edge"])
 
-    for bc, want in (([P] * 4, (512, 147, 147)), ([W] * 4, (512, 147, 137)),
-                     ([W, W, P, P], (512, 147, 137)),
+    for bc, want in (([P] * 4, (512, 147, 147)), ([W] * 4, (512, 147, 147)),
+                     ([W, W, P, P], (512, 147, 147)),
                      ([P, P, W, W], (512, 147, 147))):
         h, got = shape(bc)
         lb.lbpc_destroy(h)
