@@ -1,6 +1,5 @@
 """The batched form: many lattices of uneven size in one persistent launch per
 step, hipGraph-captured steps and the tile autotuner, through the C ABI."""
-import os
 
 import numpy as np
 import pytest

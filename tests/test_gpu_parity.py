@@ -6,7 +6,6 @@ rho and T (pointwise) and in u (normalised by max |u| of the oracle, since u
 vanishes in places).  The arithmetic differs only in rounding order and FMA
 contraction, so the two agree to a few ulp per step.
 """
-import os
 
 import numpy as np
 import pytest

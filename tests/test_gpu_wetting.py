@@ -6,7 +6,6 @@ heated-surface set-up), a batch mixing wetting and neutral lattices, and the
 reduced-precision forms."""
 import json
 
-import numpy as np
 import pytest
 
 import oracle as O
