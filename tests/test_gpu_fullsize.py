@@ -244,3 +244,63 @@ def test_16384_fp64_offsets_beyond_2_31_elements():
             assert e < 1e-12, (cx, cy, k, e)
     print(f"\n[fullsize] 16384^2 FP64 worst window error {worst:.2e}",
           flush=True)
+
+
+def _split_hist(state, nh):
+    """Saved state with nh history arrays after f and g (phi, then for the
+    BGK form T v_x and T v_y of the previous step)."""
+    w = state.view(np.float64)
+    n = N * N
+    f = w[:9 * n].reshape(9, N, N)
+    g = w[9 * n:18 * n].reshape(9, N, N)
+    hist = w[18 * n:(18 + nh) * n].reshape(nh, N, N)
+    meta = w[(18 + nh) * n:(18 + nh) * n + 3]
+    return f, g, hist, int(meta[:1].view(np.int64)[0]), float(meta[1]), \
+        int(meta[2:3].view(np.int64)[0])
+
+
+@pytest.mark.parametrize("model", [I.THERMAL_GONG_CHENG,
+                                   I.THERMAL_IMPROVED_BGK])
+def test_spinodal_4096_other_models_in_windows(model):
+    """The Gong-Cheng model and the BGK form of the improved model at the
+    benchmark's full size, FP64, in the launch configuration bench.py times
+    for them: 20 steps, then one more GPU step compared in the windows of
+    the improved model's test (the BGK form's T v history travels with the
+    window)."""
+    from paper_1709_04400_amd import lbpc
+    cfg, fl = I.spinodal(N, precision=I.FP64)
+    cfg["thermal_model"] = model
+    nh = 3 if model == I.THERMAL_IMPROVED_BGK else 1
+    g = lbpc.Simulation(cfg)
+    g.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
+    del fl
+    g.step(20)
+    s0 = g.save_state()
+    g.step(1)
+    s1 = g.save_state()
+    g.close()
+    f0, g0, h0, valid, rho_ave, step = _split_hist(s0, nh)
+    f1, g1, _, _, _, _ = _split_hist(s1, nh)
+    ocfg = dict(cfg, nx=WIN, ny=WIN)
+    inner = slice(MARGIN, WIN - MARGIN)
+    worst = 0.0
+    for cx, cy in CENTRES:
+        st0 = {"f": _window(f0, cx, cy), "g": _window(g0, cx, cy),
+               "phi_prev": _window(h0[0], cx, cy), "phi_valid": valid,
+               "rho_ave": rho_ave, "step": step}
+        if nh == 3:
+            st0["tv_prev"] = np.ascontiguousarray(_window(h0[1:3], cx, cy))
+        o = O.Oracle(ocfg)
+        o.set_state(st0)
+        o.step(1)
+        st = o.get_state()
+        fo = st["f"].reshape(9, WIN, WIN)[:, inner, inner]
+        go = st["g"].reshape(9, WIN, WIN)[:, inner, inner]
+        fg = _window(f1, cx, cy)[:, inner, inner]
+        gg = _window(g1, cx, cy)[:, inner, inner]
+        e_f = np.abs(fg - fo).max() / np.abs(fo).max()
+        e_g = np.abs(gg - go).max() / np.abs(go).max()
+        worst = max(worst, e_f, e_g)
+        assert e_f < TOL[I.FP64] and e_g < TOL[I.FP64], (cx, cy, e_f, e_g)
+    print(f"\n[fullsize] model {model} worst window error {worst:.2e}",
+          flush=True)
