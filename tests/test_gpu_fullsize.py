@@ -138,20 +138,26 @@ def _cut_window(a, x0, y0):
     return a[..., y0:y0 + WIN, x0:x0 + WIN]
 
 
-def test_walled_4096_fp64_edge_runs_in_windows():
-    """The 4096 x 4096 spinodal walled on all four sides, FP64, with the two
-    x-edge strips on 137-row runs and the others on 147-row runs (all in one
-    wave).  After 20 steps one more GPU step is compared in windows: at each
-    wall (the oracle window keeps that wall; a cut side gets a wall or the
-    periodic pair and is excluded with the dependence margin), at a corner,
-    and where an edge strip's run boundary (y = 1918) and an interior
-    strip's (y = 1911) meet across a strip boundary (x = 456)."""
+@pytest.mark.parametrize("prec", [I.FP64, I.FP32, I.FP32_SHIFTED,
+                                  I.FP16_SHIFTED])
+def test_walled_4096_in_windows(prec):
+    """The 4096 x 4096 spinodal walled on all four sides.  FP64 with the two
+    x-edge strips on 137-row runs and the others on 147-row runs (one wave);
+    the FP32 forms with their default tiles (their edge waves take the short
+    x-side path in rows away from the y sides).  After 20 steps one more GPU
+    step is compared in windows: at each wall (the oracle window keeps that
+    wall; a cut side gets a wall or the periodic pair and is excluded with
+    the dependence margin), at a corner, and where an edge strip's run
+    boundary (y = 1918) and an interior strip's (y = 1911) meet across a
+    strip boundary (x = 456).  FP64 compares f and g, every form rho and T,
+    within the bounds of the periodic test."""
+    import os
     from paper_1709_04400_amd import lbpc
     W_, P_ = I.BC_WALL, I.BC_PERIODIC
-    import os
-    cfg, fl = I.spinodal(N, precision=I.FP64)
+    cfg, fl = I.spinodal(N, precision=prec)
     cfg["bc"] = [W_] * 4
-    env = {"LBPC_TILE_BW": "512", "LBPC_TILE_H": "147", "LBPC_TILE_HE": "137"}
+    env = ({"LBPC_TILE_BW": "512", "LBPC_TILE_H": "147",
+            "LBPC_TILE_HE": "137"} if prec == I.FP64 else {})
     old = {k: os.environ.get(k) for k in env}
     os.environ.update(env)
     try:
@@ -162,7 +168,9 @@ def test_walled_4096_fp64_edge_runs_in_windows():
                 os.environ.pop(k, None)
             else:
                 os.environ[k] = v
-    assert g.tiles() == {"block_width": 512, "rows": 147, "rows_edge": 137}
+    if prec == I.FP64:
+        assert g.tiles() == {"block_width": 512, "rows": 147,
+                             "rows_edge": 137}
     g.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
     del fl
     g.step(20)
@@ -180,7 +188,8 @@ def test_walled_4096_fp64_edge_runs_in_windows():
         real = [x0 == 0, x0 + WIN == N, y0 == 0, y0 + WIN == N]
         bx = W_ if real[0] or real[1] else P_
         by = W_ if real[2] or real[3] else P_
-        ocfg = dict(cfg, nx=WIN, ny=WIN, bc=[bx, bx, by, by])
+        ocfg = dict(cfg, nx=WIN, ny=WIN, bc=[bx, bx, by, by],
+                    precision=I.FP64)
         o = O.Oracle(ocfg)
         o.set_state({"f": _cut_window(f0, x0, y0),
                      "g": _cut_window(g0, x0, y0),
@@ -194,11 +203,17 @@ def test_walled_4096_fp64_edge_runs_in_windows():
         go = st["g"].reshape(9, WIN, WIN)[:, ys, xs]
         fg = _cut_window(f1, x0, y0)[:, ys, xs]
         gg = _cut_window(g1, x0, y0)[:, ys, xs]
-        e_f = np.abs(fg - fo).max() / np.abs(fo).max()
-        e_g = np.abs(gg - go).max() / np.abs(go).max()
-        worst = max(worst, e_f, e_g)
-        assert e_f < TOL[I.FP64] and e_g < TOL[I.FP64], (x0, y0, e_f, e_g)
-    print(f"[fullsize] walled FP64 worst window error {worst:.2e}", flush=True)
+        e_rho = np.abs(fg.sum(0) - fo.sum(0)).max() / np.abs(fo.sum(0)).min()
+        e_T = np.abs(gg.sum(0) - go.sum(0)).max() / np.abs(go.sum(0)).min()
+        worst = max(worst, e_rho, e_T)
+        assert e_rho < TOL[prec] and e_T < TOL[prec], (x0, y0, e_rho, e_T)
+        if prec == I.FP64:
+            e_f = np.abs(fg - fo).max() / np.abs(fo).max()
+            e_g = np.abs(gg - go).max() / np.abs(go).max()
+            worst = max(worst, e_f, e_g)
+            assert e_f < TOL[prec] and e_g < TOL[prec], (x0, y0, e_f, e_g)
+    print(f"\n[fullsize] walled prec={prec} worst window error {worst:.2e}",
+          flush=True)
 
 
 def test_16384_fp64_offsets_beyond_2_31_elements():
