@@ -60,10 +60,11 @@ def gpu_run(n, prec, steps, warmup, per_launch=40, model=0):
     torch.cuda.synchronize()
     kern_ms = sum(a.elapsed_time(b) for a, b in evs) / per_launch
     d = sim.diag()
+    tiles = sim.tiles()
     sim.close()
     if d["nonfinite"]:
         raise RuntimeError("non-finite state in the benchmark run")
-    return ms_total / steps, kern_ms, cfg
+    return ms_total / steps, kern_ms, dict(cfg, tiles=tiles)
 
 
 def batch_run(count, steps, warmup, tiles=None):
@@ -111,22 +112,168 @@ def batch_run(count, steps, warmup, tiles=None):
     return ms, nodes, tune
 
 
-def cpu_baseline(n_sample=512, steps=150):
-    """The FP64 oracle, single thread, on a crop of the same recipe."""
+def ceiling_run(n, elem_bytes, tiles, reps=20, warmup=5):
+    """What the HBM delivers here to (a) a plain 16-byte-vector device copy
+    of the state's size and (b) a pull-stream kernel with exactly the step's
+    access pattern, tile shape and march order and no arithmetic
+    (csrc/lbpc_probe.hip); both timed with HIP events on the launch stream.
+    The pattern kernel moves the step's algorithmic bytes per launch."""
+    import ctypes
+    import torch
+    from paper_1709_04400_amd import build as B
+    probe = ctypes.CDLL(B.PROBE_LIB)
+    vp = ctypes.c_void_p
+    probe.lbpc_probe_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    probe.lbpc_probe_pattern.argtypes = [vp] * 6 + [ctypes.c_int] * 6 + [vp]
+    N = n * n
+    dt = torch.float64 if elem_bytes == 8 else torch.float32
+    dist = [torch.ones(9 * N, dtype=dt, device="cuda") for _ in range(4)]
+    phi = [torch.ones(N, dtype=dt, device="cuda") for _ in range(2)]
+    stream = torch.cuda.current_stream()
+    sp = vp(stream.cuda_stream)
+    bw, rows = tiles["block_width"], tiles["rows"]
+    nbx = -(-n // (bw - 4))
+    W = -(-n // nbx)                        # balanced strips, as the step
+
+    def pattern(k):
+        a, b = (0, 2) if k % 2 == 0 else (2, 0)
+        st = probe.lbpc_probe_pattern(
+            dist[a].data_ptr(), dist[a + 1].data_ptr(), dist[b].data_ptr(),
+            dist[b + 1].data_ptr(), phi[k % 2].data_ptr(),
+            phi[1 - k % 2].data_ptr(), n, n, elem_bytes, bw, W, rows, sp)
+        if st != 0:
+            raise RuntimeError(f"pattern probe failed ({st})")
+
+    nbytes = 9 * N * elem_bytes * 2          # f and g of one buffer
+
+    def copy(k):
+        a, b = (0, 2) if k % 2 == 0 else (2, 0)
+        src, dst = dist[a], dist[b]
+        if probe.lbpc_probe_copy(src.data_ptr(), dst.data_ptr(),
+                                 dist[a].numel() * elem_bytes, sp) != 0:
+            raise RuntimeError("copy probe failed")
+        if probe.lbpc_probe_copy(dist[a + 1].data_ptr(),
+                                 dist[b + 1].data_ptr(),
+                                 dist[a].numel() * elem_bytes, sp) != 0:
+            raise RuntimeError("copy probe failed")
+
+    out = {}
+    for name, fn, moved in (
+            ("pattern", pattern, (36 + 2) * elem_bytes * N),
+            ("copy", copy, 2 * nbytes)):
+        for k in range(warmup):
+            fn(k)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for k in range(reps):
+            fn(k)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": round(ms, 5), "GBs": round(moved / ms / 1e6, 1),
+                     "bytes": moved}
+    del dist, phi
+    torch.cuda.empty_cache()
+    return {"copy_GBs": out["copy"]["GBs"],
+            "pattern_GBs": out["pattern"]["GBs"],
+            "pattern_ms": out["pattern"]["ms"],
+            "copy_ms_per_GB": round(out["copy"]["ms"] / (2 * nbytes / 1e9),
+                                    5),
+            "pattern_tiles": {"block_width": bw, "strip": W, "rows": rows},
+            "what": "pattern: pull-stream with the step's layout, tiles and "
+                    "march, no arithmetic, same algorithmic bytes per launch; "
+                    "copy: plain device copy of the state's f and g"}
+
+
+def _host_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return model, os.cpu_count(), usable
+
+
+def _oracle_mlups(job):
+    """One oracle process: (recipe, args, warm steps, timed steps) ->
+    (lattice updates, seconds)."""
     import oracle
     from paper_1709_04400_amd import inputs
-    cfg, fl = inputs.spinodal(n_sample)
+    recipe, kwargs, warm, steps = job
+    cfg, fl = getattr(inputs, recipe)(**kwargs)
     o = oracle.Oracle(cfg)
     o.init_fields(**fl)
-    o.step(2)
+    o.step(warm)
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
-    return {"value": n_sample * n_sample * steps / dt / 1e6, "unit": "MLUPS",
-            "cores": 1, "kind": "oracle",
-            "sample": f"spinodal recipe (seed 4400) on a {n_sample}x{n_sample} "
-                      f"periodic lattice, {steps} steps, single thread, "
-                      f"{dt:.1f} s"}
+    return cfg["nx"] * cfg["ny"] * steps, dt
+
+
+def cpu_baseline(n_sample=512, steps=30):
+    """The FP64 oracle as it stands (single-threaded C) on the host cores:
+    the headline value runs one oracle process per usable core, each on its
+    own 512 x 512 crop of the spinodal recipe (a different seed per
+    process), and sums their lattice updates over the slowest process's
+    time; beside it the single-core rate on each workload of the suite (a
+    bounded number of steps each) and the all-cores rate over the batched
+    sweep's first lattices."""
+    import multiprocessing as mp
+    from paper_1709_04400_amd import inputs
+    model, ncpu, usable = _host_info()
+    cores = max(1, min(usable or 1, 16))
+    ctx = mp.get_context("spawn")
+    jobs = [("spinodal", {"n": n_sample, "seed": 4400 + k}, 2, steps)
+            for k in range(cores)]
+    with ctx.Pool(cores) as pool:
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_mlups, jobs)
+        wall = time.perf_counter() - t0
+    lups = sum(r[0] for r in res)
+    slowest = max(r[1] for r in res)
+    per_config = {}
+    single = [
+        ("static_droplet_100", "static_droplet", {}, 20, 200),
+        ("evaporation_300", "evaporation", {}, 5, 60),
+        ("boiling_400x800", "bubble", {}, 2, 12),
+        ("spinodal_512_crop", "spinodal", {"n": 512}, 2, 20),
+    ]
+    for name, recipe, kw, warm, st in single:
+        lu, dt = _oracle_mlups((recipe, kw, warm, st))
+        per_config[name] = {"MLUPS": round(lu / dt / 1e6, 3), "steps": st,
+                            "cores": 1}
+    sizes, tws = inputs.batch_sizes()
+    bjobs = [("heated_droplet", {"n": sz, "radius": 0.2 * sz,
+                                 "T_w_over_Ts": tw}, 2, 100)
+             for sz, tw in list(zip(sizes, tws))[:cores]]
+    with ctx.Pool(cores) as pool:
+        t0 = time.perf_counter()
+        bres = pool.map(_oracle_mlups, bjobs)
+        bwall = time.perf_counter() - t0
+    per_config["batched_sweep_all_cores"] = {
+        "MLUPS": round(sum(r[0] for r in bres) / max(r[1] for r in bres)
+                       / 1e6, 3),
+        "lattices": len(bjobs), "steps": 100, "cores": cores}
+    return {"value": round(lups / slowest / 1e6, 3), "unit": "MLUPS",
+            "cores": cores, "kind": "oracle",
+            "sample": f"spinodal recipe, {cores} processes (one per usable "
+                      f"core), each a {n_sample}x{n_sample} periodic crop "
+                      f"with its own seed, {steps} steps, FP64 single-"
+                      f"threaded oracle per process; slowest process "
+                      f"{slowest:.1f} s (wall {wall:.1f} s)",
+            "single_core_MLUPS": round(res[0][0] / res[0][1] / 1e6, 3),
+            "host": {"cpu_model": model, "logical_cpus": ncpu,
+                     "usable_cpus": usable},
+            "per_config": per_config}
 
 
 def main():
@@ -138,6 +285,8 @@ def main():
     ap.add_argument("--variants", type=int, default=1,
                     help="also time the reduced-precision storage forms")
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--ceiling", type=int, default=1,
+                    help="time the copy and access-pattern probes")
     ap.add_argument("--batch", type=int, default=256,
                     help="lattices in the batched sweep (0: skip it)")
     ap.add_argument("--per-launch", type=int, default=40)
@@ -158,6 +307,7 @@ def main():
 
     ms, kern_ms, cfg = gpu_run(args.n, 0, args.steps, args.warmup,
                                args.per_launch)
+    ceiling = ceiling_run(args.n, 8, cfg["tiles"]) if args.ceiling else None
     nodes = args.n * args.n
     mlups = nodes / ms / 1e3
     alg_bytes = BYTES_PER_LUP[0] * nodes
@@ -180,38 +330,55 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "kernel_avg_ms": round(kern_ms, 5),
-                     "alg_bytes_per_launch": alg_bytes},
+                     "alg_bytes_per_launch": alg_bytes,
+                     "alg_bytes_per_lup": BYTES_PER_LUP[0],
+                     "achieved_from_ms_per_step": round(
+                         alg_bytes / (ms * 1e-3) / 1e9, 1)},
     }
+    if ceiling:
+        out["roofline"]["ceiling"] = ceiling
+        out["roofline"]["ceiling_GBs"] = ceiling["pattern_GBs"]
+        out["roofline"]["frac_of_ceiling"] = round(
+            achieved / ceiling["pattern_GBs"], 4)
     if args.variants:
         var = {}
+
+        def entry(vms, vk, bpl, dtype):
+            # frac from the same timer as MLUPS (ms_per_step); the per-launch
+            # event average beside it
+            vb = bpl * nodes / (vms * 1e-3) / 1e9
+            return {"MLUPS": round(nodes / vms / 1e3, 1),
+                    "ms_per_step": round(vms, 5), "dtype": dtype,
+                    "alg_GBs": round(vb, 1),
+                    "frac": round(vb / HBM_PEAK_GBS, 4),
+                    "kernel_avg_ms": round(vk, 5),
+                    "frac_per_launch": round(
+                        bpl * nodes / (vk * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "bytes_per_lup": bpl}
         for prec in (1, 2, 3):
-            vms, vk, _ = gpu_run(args.n, prec, max(args.steps // 4, 50),
-                                 args.warmup)
-            vb = BYTES_PER_LUP[prec] * nodes / (vk * 1e-3) / 1e9
-            var[PREC_NAME[prec]] = {
-                "MLUPS": round(nodes / vms / 1e3, 1),
-                "ms_per_step": round(vms, 5), "dtype": PREC_DTYPE[prec],
-                "alg_GBs": round(vb, 1),
-                "frac": round(vb / HBM_PEAK_GBS, 4),
-                "bytes_per_lup": BYTES_PER_LUP[prec]}
+            vms, vk, vcfg = gpu_run(args.n, prec, max(args.steps // 4, 50),
+                                    args.warmup)
+            var[PREC_NAME[prec]] = entry(vms, vk, BYTES_PER_LUP[prec],
+                                         PREC_DTYPE[prec])
+            if prec == 1 and args.ceiling:
+                c32 = ceiling_run(args.n, 4, vcfg["tiles"])
+                var["FP32"]["ceiling_GBs"] = c32["pattern_GBs"]
+                var["FP32"]["frac_of_ceiling"] = round(
+                    var["FP32"]["alg_GBs"] / c32["pattern_GBs"], 4)
+                var["FP32"]["ceiling"] = c32
         # the other thermal models on the same workload (FP64): the
-        # Gong-Cheng BGK collision, and the BGK form of the improved model,
-        # which also reads and writes T v of the previous step
-        for model, name, bpl in ((2, "GONG_CHENG_FP64", BYTES_PER_LUP[0]),
-                                 (3, "IMPROVED_BGK_FP64",
-                                  BYTES_PER_LUP[0] + 4 * 8)):
+        # Gong-Cheng BGK collision, which writes phi but reads no history
+        # (36 x 8 + 8 B), and the BGK form of the improved model, which also
+        # reads and writes T v of the previous step (36 x 8 + 6 x 8 B)
+        for model, name, bpl in ((2, "GONG_CHENG_FP64", 36 * 8 + 8),
+                                 (3, "IMPROVED_BGK_FP64", 36 * 8 + 6 * 8)):
             try:
                 vms, vk, _ = gpu_run(args.n, 0, max(args.steps // 8, 50),
                                      args.warmup, model=model)
             except RuntimeError as e:
                 var[name] = {"error": str(e)}
                 continue
-            vb = bpl * nodes / (vk * 1e-3) / 1e9
-            var[name] = {
-                "MLUPS": round(nodes / vms / 1e3, 1),
-                "ms_per_step": round(vms, 5), "dtype": "f64",
-                "alg_GBs": round(vb, 1), "frac": round(vb / HBM_PEAK_GBS, 4),
-                "bytes_per_lup": bpl}
+            var[name] = entry(vms, vk, bpl, "f64")
         out["variants"] = var
     if args.batch:
         bsteps = max(args.steps // 10, 50)

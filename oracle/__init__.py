@@ -82,10 +82,16 @@ _lib = None
 
 
 def lib():
+    """The loaded oracle library.  LBPO_LIB in the environment names another
+    build of the oracle's source to load instead (the planted-slip test
+    loads scratch copies with a deliberate mistake this way)."""
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(LIB_PATH)
+        path = os.environ.get("LBPO_LIB")
+        if not path:
+            build()
+            path = LIB_PATH
+        L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         L.lbpo_create.argtypes = [ctypes.POINTER(Config),
                                   ctypes.POINTER(ctypes.c_void_p)]

@@ -9,6 +9,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbpc.so")
 SOURCES = ["lbpc_api.cpp", "lbpc_batch.cpp", "lbpc_step.hip", "lbpc_aux.hip"]
+# memory-ceiling probes the benchmark times beside the step (own library)
+PROBE_SOURCE = "lbpc_probe.hip"
+PROBE_LIB = os.path.join(HERE, "liblbpc_probe.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -36,6 +39,13 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    tmp = PROBE_LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + FLAGS + ["-shared", "-o", tmp,
+                             os.path.join(CSRC, PROBE_SOURCE)]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, PROBE_LIB)
     return LIB
 
 

@@ -154,6 +154,8 @@ lbpc_status prepare_step(lbpc_handle* h, bool tuning) {
   if (!h->tiled) return LBPC_OK;
   if (!h->table_valid) {
     std::vector<std::array<int, 4>> work = xcd_order(tile_list(h->base));
+    if (work.size() > h->L.work_capacity)
+      return fail(h, LBPC_ERR_ARG, "tile list exceeds the workspace's capacity");
     HIP_TRY(h,
             hipMemcpyAsync(at(h, h->L.work), work.data(),
                            work.size() * sizeof(work[0]),

@@ -392,8 +392,10 @@ inline void default_tiles(const lbpc_config& c, bool tiled, int cus, int& bw,
                     (c.precision != LBPC_FP16_SHIFTED && !tiled);
   bw = env_int("LBPC_TILE_BW", wide ? 512 : 256);
   if (!valid_block_width(bw)) bw = 256;
+  // runs shorter than 4 rows are not supported (the tile list and its
+  // workspace capacity assume at least 4): such a setting is ignored
   rows = env_int("LBPC_TILE_H", 0);
-  if (rows > 0) {
+  if (rows >= 4) {
     rows_edge = env_int("LBPC_TILE_HE", rows);
     if (rows_edge < 4) rows_edge = rows;
   } else {

@@ -90,7 +90,7 @@ def test_random_distinct_rates():
     sg[5] = sg[3]
     cfg, fl = I.static_droplet(64, 64, 16.0)
     cfg.update(s_f=sf, s_g=sg, gx=2e-5, gy=-1e-5)
-    _assert_ok(run_pair(cfg, fl, 500, chunks=2))
+    _assert_ok(run_pair(cfg, fl, 1000, chunks=2))
 
 
 def test_compromised_model():

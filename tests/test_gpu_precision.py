@@ -182,11 +182,12 @@ def test_bubble_departure_time():
     ref = _departure(I.FP64)
     assert ref is not None, "FP64 bubble did not depart"
     out = {"FP64": ref}
-    for prec in (I.FP32, I.FP16_SHIFTED):
+    for prec in (I.FP32, I.FP32_SHIFTED, I.FP16_SHIFTED):
         s = _departure(prec)
         out[NAMES[prec]] = {"step": s,
                             "rel_err": None if s is None else
                             abs(s - ref) / ref}
     _report("bubble_departure_step", out)
-    assert out["FP32"]["step"] is not None
-    assert out["FP32"]["rel_err"] < 0.05
+    for name in ("FP32", "FP32_SHIFTED"):
+        assert out[name]["step"] is not None, name
+        assert out[name]["rel_err"] < 0.05, (name, out[name])
