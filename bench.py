@@ -59,12 +59,25 @@ def gpu_run(n, prec, steps, warmup, per_launch=40, model=0):
         b.record(stream)
     torch.cuda.synchronize()
     kern_ms = sum(a.elapsed_time(b) for a, b in evs) / per_launch
+    # a step that also reduces the FP64 diagnostics (lbpc_step_diag: the
+    # diagnostic step kernel, the final reduction and the 64-byte copy),
+    # against the plain step's launch time above
+    dms = []
+    for _ in range(8):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        d = sim.step_diag(1)
+        b.record(stream)
+        torch.cuda.synchronize()
+        dms.append(a.elapsed_time(b))
     d = sim.diag()
     tiles = sim.tiles()
     sim.close()
     if d["nonfinite"]:
         raise RuntimeError("non-finite state in the benchmark run")
-    return ms_total / steps, kern_ms, dict(cfg, tiles=tiles)
+    return ms_total / steps, kern_ms, dict(
+        cfg, tiles=tiles, diag_step_ms=sorted(dms)[len(dms) // 2])
 
 
 def batch_run(count, steps, warmup, tiles=None):
@@ -113,54 +126,35 @@ def batch_run(count, steps, warmup, tiles=None):
 
 
 def ceiling_run(n, elem_bytes, tiles, reps=20, warmup=5):
-    """What the HBM delivers here to (a) a plain 16-byte-vector device copy
-    of the state's size and (b) a pull-stream kernel with exactly the step's
-    access pattern, tile shape and march order and no arithmetic
-    (csrc/lbpc_probe.hip); both timed with HIP events on the launch stream.
-    The pattern kernel moves the step's algorithmic bytes per launch."""
+    """What the HBM delivers here, timed with HIP events on the launch stream
+    in this process (csrc/lbpc_probe.hip): (a) streaming kernels over the
+    state's f and g arrays (copy, the same with non-temporal accesses, read
+    only, write only; the best of three grid sizes each) and (b) a pull-
+    stream kernel with exactly the step's access pattern, tile shape and
+    march order and no arithmetic, which moves the step's algorithmic bytes
+    per launch.  The ceiling for the step's mixed read/write traffic is the
+    faster of the copy and the pattern kernel."""
     import ctypes
     import torch
     from paper_1709_04400_amd import build as B
     probe = ctypes.CDLL(B.PROBE_LIB)
     vp = ctypes.c_void_p
-    probe.lbpc_probe_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
-    probe.lbpc_probe_pattern.argtypes = [vp] * 6 + [ctypes.c_int] * 6 + [vp]
+    probe.lbpc_probe_stream.argtypes = [ctypes.c_int, vp, vp, ctypes.c_size_t,
+                                        ctypes.c_int, vp]
+    probe.lbpc_probe_pattern.argtypes = [vp] * 7 + [ctypes.c_int] * 6 + [vp]
     N = n * n
     dt = torch.float64 if elem_bytes == 8 else torch.float32
     dist = [torch.ones(9 * N, dtype=dt, device="cuda") for _ in range(4)]
     phi = [torch.ones(N, dtype=dt, device="cuda") for _ in range(2)]
+    sink = torch.empty(19 * n, dtype=dt, device="cuda")
     stream = torch.cuda.current_stream()
     sp = vp(stream.cuda_stream)
     bw, rows = tiles["block_width"], tiles["rows"]
     nbx = -(-n // (bw - 4))
     W = -(-n // nbx)                        # balanced strips, as the step
+    arr_bytes = 9 * N * elem_bytes
 
-    def pattern(k):
-        a, b = (0, 2) if k % 2 == 0 else (2, 0)
-        st = probe.lbpc_probe_pattern(
-            dist[a].data_ptr(), dist[a + 1].data_ptr(), dist[b].data_ptr(),
-            dist[b + 1].data_ptr(), phi[k % 2].data_ptr(),
-            phi[1 - k % 2].data_ptr(), n, n, elem_bytes, bw, W, rows, sp)
-        if st != 0:
-            raise RuntimeError(f"pattern probe failed ({st})")
-
-    nbytes = 9 * N * elem_bytes * 2          # f and g of one buffer
-
-    def copy(k):
-        a, b = (0, 2) if k % 2 == 0 else (2, 0)
-        src, dst = dist[a], dist[b]
-        if probe.lbpc_probe_copy(src.data_ptr(), dst.data_ptr(),
-                                 dist[a].numel() * elem_bytes, sp) != 0:
-            raise RuntimeError("copy probe failed")
-        if probe.lbpc_probe_copy(dist[a + 1].data_ptr(),
-                                 dist[b + 1].data_ptr(),
-                                 dist[a].numel() * elem_bytes, sp) != 0:
-            raise RuntimeError("copy probe failed")
-
-    out = {}
-    for name, fn, moved in (
-            ("pattern", pattern, (36 + 2) * elem_bytes * N),
-            ("copy", copy, 2 * nbytes)):
+    def timed(fn):
         for k in range(warmup):
             fn(k)
         e0 = torch.cuda.Event(enable_timing=True)
@@ -170,20 +164,49 @@ def ceiling_run(n, elem_bytes, tiles, reps=20, warmup=5):
             fn(k)
         e1.record(stream)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        out[name] = {"ms": round(ms, 5), "GBs": round(moved / ms / 1e6, 1),
-                     "bytes": moved}
-    del dist, phi
+        return e0.elapsed_time(e1) / reps
+
+    def pattern(k):
+        a, b = (0, 2) if k % 2 == 0 else (2, 0)
+        st = probe.lbpc_probe_pattern(
+            dist[a].data_ptr(), dist[a + 1].data_ptr(), dist[b].data_ptr(),
+            dist[b + 1].data_ptr(), phi[k % 2].data_ptr(),
+            phi[1 - k % 2].data_ptr(), sink.data_ptr(), n, n, elem_bytes,
+            bw, W, rows, sp)
+        if st != 0:
+            raise RuntimeError(f"pattern probe failed ({st})")
+
+    def stream_fn(kind, blocks):
+        def fn(k):
+            a, b = (0, 2) if k % 2 == 0 else (2, 0)
+            for src, dst in ((dist[a], dist[b]), (dist[a + 1], dist[b + 1])):
+                if probe.lbpc_probe_stream(kind, src.data_ptr(),
+                                           dst.data_ptr(), arr_bytes, blocks,
+                                           sp) != 0:
+                    raise RuntimeError("stream probe failed")
+        return fn
+
+    out = {}
+    pat_ms = timed(pattern)
+    out["pattern_GBs"] = round((36 + 2) * elem_bytes * N / pat_ms / 1e6, 1)
+    out["pattern_ms"] = round(pat_ms, 5)
+    for kind, name, factor in ((0, "copy", 2), (1, "copy_nontemporal", 2),
+                               (2, "read_only", 1), (3, "write_only", 1)):
+        best = None
+        for blocks in (2048, 8192, 32768):
+            ms = timed(stream_fn(kind, blocks))
+            gbs = factor * 2 * arr_bytes / ms / 1e6
+            if best is None or gbs > best[0]:
+                best = (gbs, blocks)
+        out[name + "_GBs"] = round(best[0], 1)
+        out[name + "_blocks"] = best[1]
+    del dist, phi, sink
     torch.cuda.empty_cache()
-    return {"copy_GBs": out["copy"]["GBs"],
-            "pattern_GBs": out["pattern"]["GBs"],
-            "pattern_ms": out["pattern"]["ms"],
-            "copy_ms_per_GB": round(out["copy"]["ms"] / (2 * nbytes / 1e9),
-                                    5),
-            "pattern_tiles": {"block_width": bw, "strip": W, "rows": rows},
-            "what": "pattern: pull-stream with the step's layout, tiles and "
-                    "march, no arithmetic, same algorithmic bytes per launch; "
-                    "copy: plain device copy of the state's f and g"}
+    out["ceiling_GBs"] = max(out["pattern_GBs"], out["copy_GBs"],
+                             out["copy_nontemporal_GBs"])
+    out["pattern_tiles"] = {"block_width": bw, "strip": W, "rows": rows}
+    out["bytes_each"] = 2 * arr_bytes
+    return out
 
 
 def _host_info():
@@ -324,7 +347,10 @@ def main():
                                "T = 0.86 Tc, rho and T with seeded uniform "
                                "noise, FP64 storage and arithmetic",
                    "nx": args.n, "ny": args.n, "precision": "FP64",
-                   "kernel": "k_step<0,false> (fused, one launch per step)"},
+                   "kernel": "k_step<0,false> (fused, one launch per step)",
+                   "diag_step_ms": round(cfg["diag_step_ms"], 5),
+                   "diag_step_over_step": round(
+                       cfg["diag_step_ms"] / kern_ms, 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -337,9 +363,9 @@ def main():
     }
     if ceiling:
         out["roofline"]["ceiling"] = ceiling
-        out["roofline"]["ceiling_GBs"] = ceiling["pattern_GBs"]
+        out["roofline"]["ceiling_GBs"] = ceiling["ceiling_GBs"]
         out["roofline"]["frac_of_ceiling"] = round(
-            achieved / ceiling["pattern_GBs"], 4)
+            achieved / ceiling["ceiling_GBs"], 4)
     if args.variants:
         var = {}
 
@@ -362,9 +388,9 @@ def main():
                                          PREC_DTYPE[prec])
             if prec == 1 and args.ceiling:
                 c32 = ceiling_run(args.n, 4, vcfg["tiles"])
-                var["FP32"]["ceiling_GBs"] = c32["pattern_GBs"]
+                var["FP32"]["ceiling_GBs"] = c32["ceiling_GBs"]
                 var["FP32"]["frac_of_ceiling"] = round(
-                    var["FP32"]["alg_GBs"] / c32["pattern_GBs"], 4)
+                    var["FP32"]["alg_GBs"] / c32["ceiling_GBs"], 4)
                 var["FP32"]["ceiling"] = c32
         # the other thermal models on the same workload (FP64): the
         # Gong-Cheng BGK collision, which writes phi but reads no history

@@ -152,7 +152,11 @@ typedef struct lbpc_config {
   uint32_t flags;         /* must be 0 (the oracle's test-only flags) */
 } lbpc_config;
 
-/* FP64 sums over the lattice at the current time level */
+/* FP64 sums over the lattice at one time level (the paper reports the
+ * droplet diameter ratio D/D0 of Sec. IV.A but defines no measure; these
+ * are the readings the library uses).  rho, T and v are the fields of the
+ * step's own arithmetic at that level (FP32 in the reduced-precision forms),
+ * summed in FP64. */
 typedef struct lbpc_diag {
   double mass;         /* sum rho */
   double sum_T;        /* sum T */
@@ -160,11 +164,13 @@ typedef struct lbpc_diag {
   double liquid_area;  /* sum clamp((rho - rho_v)/(rho_l - rho_v), 0, 1) */
   double radius;       /* sqrt(liquid_area / pi) */
   double radius_count; /* sqrt(#{rho > (rho_l + rho_v)/2} / pi) */
-  double max_speed;    /* max |v| (FP64 max over nodes) */
-  double sum_S0;       /* reserved (0) */
-  double sum_Fx, sum_Fy; /* reserved (0) */
-  int64_t step;        /* steps taken since lbpc_init_fields */
-  int32_t nonfinite;   /* 1 if a non-finite rho or T was seen */
+  double max_speed;    /* max |v| */
+  double sum_S0;       /* sum of the thermal source S0 of Eq. (46) of the
+                        * step taken from this level (sum T of the next
+                        * level is sum T + sum S0 on periodic lattices) */
+  int64_t step;        /* the time level: steps since lbpc_init_fields */
+  int32_t nonfinite;   /* 1 if a non-finite value or an invalid state
+                        * (flagged by a step) was seen */
   int32_t pad;
 } lbpc_diag;
 
@@ -194,8 +200,10 @@ lbpc_status lbpc_init_fields(lbpc_handle *h, const double *rho,
  * waiting.  With LBPC_GRAPH=1 in the environment at lbpc_create and a
  * non-NULL stream, steady-state pairs of steps are replayed from a captured
  * hipGraph of one ping-pong period (same results; on MI355X eager launches
- * measured slightly faster, so it is off by default).  Each step checks every node's state (psi^2 >= 0, 0 < rho < 1/b,
- * finite T, as the reference implementation does) and flags a violation.
+ * measured slightly faster, so it is off by default).  Each step checks
+ * every node's state (psi^2 >= 0, 0 < rho < 1/b, finite T: the conditions
+ * under which psi of Eq. (56) and the collision are defined) and flags a
+ * violation.
  * A flag set by a step that has completed makes lbpc_step return
  * LBPC_ERR_NUMERIC without enqueuing; every synchronising call
  * (lbpc_get_rho_u_T, lbpc_get_diag, lbpc_save_state) reports it exactly.
@@ -231,9 +239,22 @@ lbpc_status lbpc_autotune(lbpc_handle *h, int32_t steps, int32_t *block_width,
 lbpc_status lbpc_get_rho_u_T(lbpc_handle *h, double *rho, double *ux,
                              double *uy, double *T);
 
-/* Waits for the stream and fills *out; returns LBPC_ERR_NUMERIC (with *out
- * filled and nonfinite = 1) when a step has flagged an invalid state. */
+/* Diagnostics of the current time level without stepping: one pass of the
+ * fused step kernel that computes the level's fields and S0 and reduces
+ * them (waves, then blocks, then a fixed-order final pass: the same result
+ * on every run) but stores nothing, so the state is left as it is.  Waits
+ * for it and fills *out; returns LBPC_ERR_NUMERIC (with *out filled and
+ * nonfinite = 1) when a step has flagged an invalid state or a value is
+ * not finite. */
 lbpc_status lbpc_get_diag(lbpc_handle *h, lbpc_diag *out);
+
+/* Enqueues n >= 1 time steps like lbpc_step; the first of them also
+ * reduces the diagnostics of the time level it starts from (the current
+ * one), on the way, in the same launch.  Returns once that first step's
+ * results are in *out (out->step is that level), while the other n - 1
+ * steps may still run.  Same values as lbpc_get_diag called before the
+ * steps.  Errors as lbpc_step and lbpc_get_diag. */
+lbpc_status lbpc_step_diag(lbpc_handle *h, int64_t n, lbpc_diag *out);
 
 /* Canonical state {f(t) [9][ny][nx], g(t) [9][ny][nx], phi(t-1) [ny][nx]}
  * as FP64 (for the BGK form of the improved model followed by T v_x and
@@ -291,10 +312,15 @@ lbpc_status lbpc_batch_autotune(lbpc_batch *b, int32_t steps,
                                 double *ms_per_step);
 /* Enqueues n coupled time steps of every lattice. */
 lbpc_status lbpc_batch_step(lbpc_batch *b, int64_t n);
-/* Per-lattice readback, as lbpc_get_rho_u_T / lbpc_get_diag (synchronising). */
+/* Per-lattice readback, as lbpc_get_rho_u_T / lbpc_get_diag (synchronising;
+ * the diagnostic pass covers every lattice of the batch). */
 lbpc_status lbpc_batch_get_rho_u_T(lbpc_batch *b, int32_t c, double *rho,
                                    double *ux, double *uy, double *T);
 lbpc_status lbpc_batch_get_diag(lbpc_batch *b, int32_t c, lbpc_diag *out);
+/* As lbpc_step_diag for every lattice: n >= 1 steps, the first of which also
+ * reduces each lattice's diagnostics of the current time level into
+ * out[0 .. count-1] (count = the number of lattices). */
+lbpc_status lbpc_batch_step_diag(lbpc_batch *b, int64_t n, lbpc_diag *out);
 /* Lattice-node updates per step summed over the batch (for throughput). */
 lbpc_status lbpc_batch_nodes(const lbpc_batch *b, int64_t *nodes);
 void lbpc_batch_destroy(lbpc_batch *b);

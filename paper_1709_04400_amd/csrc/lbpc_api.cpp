@@ -41,9 +41,12 @@ struct lbpc_handle {
   int nwork, grid;
   StepParams table_host[2];
   // invalid-state flag written by the step kernel: host-mapped pinned
-  // memory, so lbpc_step can read it without waiting
+  // memory, so lbpc_step can read it without waiting; the diagnostic
+  // results are copied into the same pinned block (res_host)
   int* bad_host;
   int* bad_dev;
+  double* res_host;
+  hipEvent_t diag_ev;  // recorded after a diagnostic's copy to res_host
   // steady-state steps are replayed from a captured graph of one ping-pong
   // period (two launches), one per starting buffer
   hipGraphExec_t graph[2];
@@ -75,11 +78,15 @@ bool flagged(const lbpc_handle* h) {
 // initialisation or a state load), and cleared there
 lbpc_status reset_flag(lbpc_handle* h) {
   if (!h->bad_host) {
-    if (hipHostMalloc(reinterpret_cast<void**>(&h->bad_host), sizeof(int),
-                      hipHostMallocMapped) != hipSuccess) {
+    // 64 bytes for the flag, then the 8 diagnostic results
+    if (hipHostMalloc(reinterpret_cast<void**>(&h->bad_host),
+                      64 + 8 * sizeof(double), hipHostMallocMapped) !=
+        hipSuccess) {
       h->bad_host = nullptr;
       return fail(h, LBPC_ERR_OOM, "pinned host flag allocation failed");
     }
+    h->res_host = reinterpret_cast<double*>(
+        reinterpret_cast<char*>(h->bad_host) + 64);
     if (hipHostGetDevicePointer(reinterpret_cast<void**>(&h->bad_dev),
                                 h->bad_host, 0) != hipSuccess) {
       (void)hipHostFree(h->bad_host);
@@ -105,6 +112,12 @@ lbpc_status hip_fail(lbpc_handle* h, hipError_t e, const char* what) {
   } while (0)
 
 void* at(lbpc_handle* h, size_t off) { return h->ws + off; }
+double* ws_part(lbpc_handle* h) {
+  return static_cast<double*>(at(h, h->L.partial));
+}
+double* ws_dout(lbpc_handle* h) {
+  return static_cast<double*>(at(h, h->L.diag_out));
+}
 
 // step parameters for the current state (input = buffer cur)
 StepParams params_now(lbpc_handle* h) {
@@ -214,6 +227,55 @@ lbpc_status enqueue_step(lbpc_handle* h, bool tuning) {
   return st == LBPC_OK ? launch_now(h, tuning) : st;
 }
 
+// A diagnostic launch of the step kernel on the current state (with stores:
+// a real step, which the caller then books; nostore: nothing is written),
+// the final reduction of its tile records, the copy of the 8 results into
+// the pinned block and an event after it.
+// Tile records of the current shape (one per tile of the launch).
+int tile_count(const lbpc_handle* h) {
+  return h->tiled ? h->nwork : h->base.nbx * h->base.nby;
+}
+
+// part: the tile records (tile_count of them), dout: the 8 results; both in
+// the workspace, or in the static scratch of the no-allocation variant.
+lbpc_status enqueue_diag(lbpc_handle* h, bool nostore, double* part,
+                         double* dout) {
+  lbpc_status st = prepare_step(h, false);
+  if (st != LBPC_OK) return st;
+  if (!h->diag_ev)
+    HIP_TRY(h, hipEventCreateWithFlags(&h->diag_ev, hipEventDisableTiming),
+            "event");
+  StepParams p = params_now(h);
+  int ntiles;
+  if (!h->tiled) {
+    ntiles = p.nbx * p.nby;
+    HIP_TRY(h, lbpc::launch_step(p, h->cfg.precision, h->stream, part,
+                                 nostore ? 1 : 0),
+            "diagnostic step kernel");
+  } else {
+    ntiles = h->nwork;
+    HIP_TRY(h,
+            lbpc::launch_step_batch(
+                static_cast<const StepParams*>(at(h, h->L.table)),
+                at(h, h->L.work), h->nwork, h->cur, h->grid,
+                h->cfg.precision, p.bw, h->stream,
+                !(p.perx && p.pery) || h->force_gen, part, nostore ? 1 : 0),
+            "diagnostic step kernel");
+  }
+  HIP_TRY(h,
+          lbpc::launch_diag_reduce(part, nullptr, 0, ntiles, 1, dout,
+                                   h->stream),
+          "diagnostic reduction");
+  HIP_TRY(h,
+          hipMemcpyAsync(h->res_host, dout, 8 * sizeof(double),
+                         hipMemcpyDeviceToHost, h->stream),
+          "copy of the diagnostics");
+  HIP_TRY(h, hipEventRecord(h->diag_ev, h->stream), "event");
+  return LBPC_OK;
+}
+
+lbpc_status run_steps(lbpc_handle* h, int64_t n);
+
 }  // namespace
 
 extern "C" {
@@ -312,6 +374,34 @@ lbpc_status lbpc_step(lbpc_handle* h, int64_t n) {
   if (!h->initialised) return fail(h, LBPC_ERR_STATE, "step before init");
   // steps already completed may have flagged an invalid state
   if (flagged(h)) return fail(h, LBPC_ERR_NUMERIC, BAD_STATE);
+  return run_steps(h, n);
+}
+
+lbpc_status lbpc_step_diag(lbpc_handle* h, int64_t n, lbpc_diag* out) {
+  if (!h) return fail(nullptr, LBPC_ERR_ARG, "handle is NULL");
+  if (n < 1 || !out) return fail(h, LBPC_ERR_ARG, "n < 1 or out is NULL");
+  if (!h->initialised) return fail(h, LBPC_ERR_STATE, "step before init");
+  if (flagged(h)) return fail(h, LBPC_ERR_NUMERIC, BAD_STATE);
+  lbpc_status st = enqueue_diag(h, false, ws_part(h), ws_dout(h));
+  if (st != LBPC_OK) return st;
+  const int64_t t0 = h->step;
+  h->cur = 1 - h->cur;
+  h->fresh = 0;
+  h->phi_valid = 1;
+  h->step += 1;
+  st = run_steps(h, n - 1);
+  HIP_TRY(h, hipEventSynchronize(h->diag_ev), "synchronise");
+  fill_diag(out, h->res_host, h->cfg.cv, t0, flagged(h));
+  if (st != LBPC_OK) return st;
+  if (out->nonfinite) return fail(h, LBPC_ERR_NUMERIC, BAD_STATE);
+  return LBPC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+lbpc_status run_steps(lbpc_handle* h, int64_t n) {
   while (n > 0) {
     // steady state (state flags fixed): pairs of steps replay the graph of
     // one ping-pong period that starts from the current buffer
@@ -356,6 +446,10 @@ lbpc_status lbpc_step(lbpc_handle* h, int64_t n) {
   }
   return LBPC_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 lbpc_status lbpc_set_tiles(lbpc_handle* h, int32_t block_width,
                            int32_t rows) {
@@ -461,34 +555,11 @@ lbpc_status lbpc_get_diag(lbpc_handle* h, lbpc_diag* out) {
   if (!h) return fail(nullptr, LBPC_ERR_ARG, "handle is NULL");
   if (!out) return fail(h, LBPC_ERR_ARG, "out is NULL");
   if (!h->initialised) return fail(h, LBPC_ERR_STATE, "diag before init");
-  double* scr = static_cast<double*>(at(h, h->L.scratch));
-  StepParams p = params_now(h);
-  HIP_TRY(h, lbpc::launch_macro(p, h->cfg.precision, scr, h->stream),
-          "macro kernels");
-  double* dout = static_cast<double*>(at(h, h->L.diag_out));
-  HIP_TRY(h,
-          lbpc::launch_diag(p, scr, h->cfg.rho_v, h->cfg.rho_l,
-                            static_cast<double*>(at(h, h->L.partial)), dout,
-                            h->stream),
-          "diagnostic kernels");
-  double r[8];
-  HIP_TRY(h,
-          hipMemcpyAsync(r, dout, sizeof(r), hipMemcpyDeviceToHost,
-                         h->stream),
-          "copy of the diagnostics");
-  HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
-  std::memset(out, 0, sizeof(*out));
-  out->mass = r[0];
-  out->sum_T = r[1];
-  out->sum_rhocvT = r[2];
-  out->liquid_area = r[3];
-  out->radius = std::sqrt(r[3] / M_PI);
-  out->radius_count = std::sqrt(r[4] / M_PI);
-  out->max_speed = r[5];
-  out->nonfinite = r[6] != 0.0 || !std::isfinite(r[0]) ||
-                   !std::isfinite(r[1]) || flagged(h);
-  out->step = h->step;
-  if (flagged(h)) return fail(h, LBPC_ERR_NUMERIC, BAD_STATE);
+  lbpc_status st = enqueue_diag(h, true, ws_part(h), ws_dout(h));
+  if (st != LBPC_OK) return st;
+  HIP_TRY(h, hipEventSynchronize(h->diag_ev), "synchronise");
+  fill_diag(out, h->res_host, h->cfg.cv, h->step, flagged(h));
+  if (out->nonfinite) return fail(h, LBPC_ERR_NUMERIC, BAD_STATE);
   return LBPC_OK;
 }
 
@@ -592,6 +663,7 @@ void lbpc_destroy(lbpc_handle* h) {
   if (!h) return;
   if (h->initialised) (void)hipStreamSynchronize(h->stream);
   drop_graphs(h);
+  if (h->diag_ev) (void)hipEventDestroy(h->diag_ev);
   if (h->bad_host) (void)hipHostFree(h->bad_host);
   delete h;
 }

@@ -1,7 +1,7 @@
 // lbpc_aux.hip -- the kernels around the fused step: initial equilibria,
-// macroscopic fields at the current time level (rho, v, T), FP64
-// diagnostic reductions and the canonical-state transfers of
-// checkpoint / restart.  None of these is on the per-step path.
+// macroscopic fields at the current time level (rho, v, T), the final pass
+// of the FP64 diagnostic reduction and the canonical-state transfers of
+// checkpoint / restart.
 #include "lbpc_device.h"
 
 namespace lbpc {
@@ -125,60 +125,41 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_macro2(StepParams p,
   io[2 * N + i] = (io[2 * N + i] + 0.5 * Fy) / rho;
 }
 
-// FP64 sums over the macro fields: per block partials [block][8] =
-// {sum rho, sum T, sum rho cv T, liquid area, count, max |v|, nonfinite, 0}
-__global__ __launch_bounds__(AUX_BLOCK) void k_diag_partial(
-    StepParams p, const double* io, double rho_v, double rho_l,
-    double* partial) {
+// Final pass of the diagnostics: block c reduces the tile records
+// [lo_c, hi_c) of lattice c (8 FP64 values each: six sums, then two maxima)
+// into out[c]; ranges holds (lo_c, hi_c) pairs, or is NULL for one lattice
+// with records [lo, hi).  Each thread takes a fixed strided subset in order
+// and the block combines them by a fixed tree, so the result does not depend
+// on scheduling.
+__global__ __launch_bounds__(AUX_BLOCK) void k_diag_reduce(
+    const double* __restrict__ part, const int* __restrict__ ranges, int lo0,
+    int hi0, double* __restrict__ out) {
   __shared__ double red[8][AUX_BLOCK];
-  const long long N = p.N;
+  const int c = blockIdx.x, t = threadIdx.x;
+  const int lo = ranges ? ranges[2 * c] : lo0;
+  const int hi = ranges ? ranges[2 * c + 1] : hi0;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (long long i = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x; i < N;
-       i += (long long)gridDim.x * AUX_BLOCK) {
-    const double rho = io[i], vx = io[N + i], vy = io[2 * N + i],
-                 T = io[3 * N + i];
-    acc[0] += rho;
-    acc[1] += T;
-    acc[2] += rho * p.cv * T;
-    double fr = (rho - rho_v) / (rho_l - rho_v);
-    fr = fr < 0.0 ? 0.0 : (fr > 1.0 ? 1.0 : fr);
-    acc[3] += fr;
-    acc[4] += rho > 0.5 * (rho_l + rho_v) ? 1.0 : 0.0;
-    const double sp = sqrt(vx * vx + vy * vy);
-    acc[5] = sp > acc[5] ? sp : acc[5];
-    if (!isfinite(rho) || !isfinite(T) || !isfinite(vx) || !isfinite(vy))
-      acc[6] = 1.0;
+  for (int i = lo + t; i < hi; i += AUX_BLOCK) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const double v = part[(long long)i * 8 + k];
+      acc[k] = k >= 6 ? (v > acc[k] ? v : acc[k]) : acc[k] + v;
+    }
   }
-  for (int k = 0; k < 8; ++k) red[k][threadIdx.x] = acc[k];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) red[k][t] = acc[k];
   __syncthreads();
-  for (int s = AUX_BLOCK / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
+  for (int st = AUX_BLOCK / 2; st > 0; st >>= 1) {
+    if (t < st) {
+#pragma unroll
       for (int k = 0; k < 8; ++k) {
-        const double o = red[k][threadIdx.x + s];
-        if (k == 5 || k == 6)
-          red[k][threadIdx.x] = o > red[k][threadIdx.x] ? o : red[k][threadIdx.x];
-        else
-          red[k][threadIdx.x] += o;
+        const double o = red[k][t + st];
+        red[k][t] = k >= 6 ? (o > red[k][t] ? o : red[k][t]) : red[k][t] + o;
       }
     }
     __syncthreads();
   }
-  if (threadIdx.x < 8) partial[blockIdx.x * 8 + threadIdx.x] = red[threadIdx.x][0];
-}
-
-// fixed-order final sum of the partials (one thread, deterministic)
-__global__ void k_diag_final(const double* partial, int nblk, double* out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int b = 0; b < nblk; ++b)
-    for (int k = 0; k < 8; ++k) {
-      const double v = partial[b * 8 + k];
-      if (k == 5 || k == 6)
-        acc[k] = v > acc[k] ? v : acc[k];
-      else
-        acc[k] += v;
-    }
-  for (int k = 0; k < 8; ++k) out[k] = acc[k];
+  if (t < 8) out[(long long)c * 8 + t] = red[t][0];
 }
 
 // canonical FP64 f(t) (which = 0..8) or g(t) (which = 9..17), one direction
@@ -283,20 +264,10 @@ hipError_t launch_macro(const StepParams& p, int prec, double* io,
   return hipGetLastError();
 }
 
-int diag_blocks(long long N) {
-  long long b = (N + AUX_BLOCK - 1) / AUX_BLOCK;
-  return (int)(b < 1024 ? b : 1024);
-}
-
-hipError_t launch_diag(const StepParams& p, const double* io, double rho_v,
-                       double rho_l, double* partial, double* out,
-                       hipStream_t s) {
-  const int nb = diag_blocks(p.N);
-  hipLaunchKernelGGL(k_diag_partial, dim3(nb), dim3(AUX_BLOCK), 0, s, p, io,
-                     rho_v, rho_l, partial);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, partial, nb, out);
+hipError_t launch_diag_reduce(const double* part, const int* ranges, int lo,
+                              int hi, int nlat, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_reduce, dim3(nlat), dim3(AUX_BLOCK), 0, s, part,
+                     ranges, lo, hi, out);
   return hipGetLastError();
 }
 

@@ -17,7 +17,7 @@ namespace {
 thread_local std::string g_berr = "";
 
 struct WorkItem {  // mirrors the device-side work item
-  int c, bx, by, pad;
+  int c, bx, by, slot;
 };
 
 // candidate tile shapes of the autotuner
@@ -32,7 +32,9 @@ struct CaseLayout {
 };
 
 struct BatchLayout {
-  size_t table, work, scratch, partial, diag_out;
+  // partial: one diagnostic record (8 FP64) per work item; ranges: the
+  // records of each lattice; diag_out: 8 FP64 results per lattice
+  size_t table, work, scratch, partial, ranges, diag_out;
   size_t work_capacity;  // items
   std::vector<CaseLayout> cases;
   size_t total;
@@ -61,10 +63,11 @@ BatchLayout plan_batch(const lbpc_config* cfgs, int n) {
   L.scratch = off;
   off += align_up(5 * maxN * sizeof(double));
   L.partial = off;
-  off += align_up((size_t)lbpc::diag_blocks((long long)maxN) * 8 *
-                  sizeof(double));
+  off += align_up(L.work_capacity * 8 * sizeof(double));
+  L.ranges = off;
+  off += align_up(2 * (size_t)n * sizeof(int));
   L.diag_out = off;
-  off += align_up(8 * sizeof(double));
+  off += align_up((size_t)n * 8 * sizeof(double));
   L.cases.resize(n);
   for (int c = 0; c < n; ++c) {
     const size_t N = (size_t)cfgs[c].nx * cfgs[c].ny;
@@ -119,9 +122,12 @@ struct lbpc_batch {
   hipGraphExec_t graph[2];
   int use_graph;
   // per-lattice invalid-state flags written by the step kernel
-  // (host-mapped pinned memory, readable without waiting)
+  // (host-mapped pinned memory, readable without waiting), and the pinned
+  // block the per-lattice diagnostic results are copied to
   int* bad_host;
   int* bad_dev;
+  double* res_host;
+  hipEvent_t diag_ev;
   std::string err;
 };
 
@@ -157,6 +163,12 @@ bool flagged(const lbpc_batch* b, int c) {
 // that touches the device)
 lbpc_status ensure_flags(lbpc_batch* b) {
   if (b->bad_host) return LBPC_OK;
+  if (hipHostMalloc(reinterpret_cast<void**>(&b->res_host),
+                    (size_t)b->n * 8 * sizeof(double), hipHostMallocDefault) !=
+      hipSuccess) {
+    b->res_host = nullptr;
+    return bfail(b, LBPC_ERR_OOM, "pinned host buffer allocation failed");
+  }
   if (hipHostMalloc(reinterpret_cast<void**>(&b->bad_host),
                     (size_t)b->n * sizeof(int), hipHostMallocMapped) !=
       hipSuccess) {
@@ -228,16 +240,27 @@ lbpc_status build_work(lbpc_batch* b) {
     return (long long)b->cfgs[x].nx * b->cfgs[x].ny >
            (long long)b->cfgs[y].nx * b->cfgs[y].ny;
   });
+  // each tile's diagnostic record is its index here, so the records of a
+  // lattice are contiguous: [ranges[2c], ranges[2c + 1])
   std::vector<WorkItem> tiles;
+  std::vector<int> ranges(2 * (size_t)b->n);
   for (int c : order) {
     int nbx, W;
     strip_shape(b->cfgs[c].nx, b->bw, true, nbx, W);
     const int nby = (b->cfgs[c].ny + b->rows - 1) / b->rows;
+    ranges[2 * c] = (int)tiles.size();
     for (int by = 0; by < nby; ++by)
-      for (int bx = 0; bx < nbx; ++bx) tiles.push_back({c, bx, by, 0});
+      for (int bx = 0; bx < nbx; ++bx)
+        tiles.push_back({c, bx, by, (int)tiles.size()});
+    ranges[2 * c + 1] = (int)tiles.size();
   }
   if (tiles.size() > b->L.work_capacity)
     return bfail(b, LBPC_ERR_OOM, "work list exceeds its reserved space");
+  BHIP(b,
+       hipMemcpyAsync(at(b, b->L.ranges), ranges.data(),
+                      ranges.size() * sizeof(int), hipMemcpyHostToDevice,
+                      b->stream),
+       "diagnostic ranges upload");
   b->work_host = xcd_order(tiles);
   b->nwork = (int)b->work_host.size();
   BHIP(b,
@@ -259,6 +282,53 @@ lbpc_status launch(lbpc_batch* b, int parity) {
        "batched step kernel");
   return LBPC_OK;
 }
+
+lbpc_status check_ready(lbpc_batch* b) {
+  for (int c = 0; c < b->n; ++c)
+    if (!b->initialised[c])
+      return bfail(b, LBPC_ERR_STATE, "step before every lattice is set");
+  for (int c = 0; c < b->n; ++c)
+    if (flagged(b, c))
+      return bfail(b, LBPC_ERR_NUMERIC,
+                   std::string(BAD_STATE) + " (lattice " + std::to_string(c) +
+                       ")");
+  return LBPC_OK;
+}
+
+// A diagnostic launch over every lattice on the current state (with stores:
+// a real step, booked by the caller; nostore: nothing is written), the
+// per-lattice final reductions, the copy of the results into the pinned
+// block and an event after it.
+lbpc_status enqueue_diag(lbpc_batch* b, bool nostore) {
+  if (b->table_fresh != b->fresh || b->table_phi_valid != b->phi_valid) {
+    lbpc_status st = upload_table(b);
+    if (st != LBPC_OK) return st;
+  }
+  if (!b->diag_ev)
+    BHIP(b, hipEventCreateWithFlags(&b->diag_ev, hipEventDisableTiming),
+         "event");
+  double* part = static_cast<double*>(at(b, b->L.partial));
+  BHIP(b,
+       lbpc::launch_step_batch(
+           static_cast<const StepParams*>(at(b, b->L.table)),
+           at(b, b->L.work), b->nwork, b->cur, b->grid, b->prec, b->bw,
+           b->stream, true, part, nostore ? 1 : 0),
+       "diagnostic step kernel");
+  double* dout = static_cast<double*>(at(b, b->L.diag_out));
+  BHIP(b,
+       lbpc::launch_diag_reduce(part,
+                                static_cast<const int*>(at(b, b->L.ranges)),
+                                0, 0, b->n, dout, b->stream),
+       "diagnostic reduction");
+  BHIP(b,
+       hipMemcpyAsync(b->res_host, dout, (size_t)b->n * 8 * sizeof(double),
+                      hipMemcpyDeviceToHost, b->stream),
+       "copy of the diagnostics");
+  BHIP(b, hipEventRecord(b->diag_ev, b->stream), "event");
+  return LBPC_OK;
+}
+
+lbpc_status run_batch_steps(lbpc_batch* b, int64_t n);
 
 }  // namespace
 
@@ -295,6 +365,8 @@ lbpc_status lbpc_batch_create(const lbpc_config* cfgs, int32_t n,
   b->L = L;
   b->bad_host = nullptr;
   b->bad_dev = nullptr;
+  b->res_host = nullptr;
+  b->diag_ev = nullptr;
   b->base.resize(n);
   for (int c = 0; c < n; ++c) derive_params(cfgs[c], b->base[c]);
   b->initialised.assign(n, 0);
@@ -429,14 +501,41 @@ lbpc_status lbpc_batch_autotune(lbpc_batch* b, int32_t steps,
 lbpc_status lbpc_batch_step(lbpc_batch* b, int64_t n) {
   if (!b) return bfail(nullptr, LBPC_ERR_ARG, "batch is NULL");
   if (n < 0) return bfail(b, LBPC_ERR_ARG, "n < 0");
-  for (int c = 0; c < b->n; ++c)
-    if (!b->initialised[c])
-      return bfail(b, LBPC_ERR_STATE, "step before every lattice is set");
-  for (int c = 0; c < b->n; ++c)
-    if (flagged(b, c))
-      return bfail(b, LBPC_ERR_NUMERIC,
-                   std::string(BAD_STATE) + " (lattice " + std::to_string(c) +
-                       ")");
+  lbpc_status st0 = check_ready(b);
+  if (st0 != LBPC_OK) return st0;
+  return run_batch_steps(b, n);
+}
+
+lbpc_status lbpc_batch_step_diag(lbpc_batch* b, int64_t n, lbpc_diag* out) {
+  if (!b) return bfail(nullptr, LBPC_ERR_ARG, "batch is NULL");
+  if (n < 1 || !out) return bfail(b, LBPC_ERR_ARG, "n < 1 or out is NULL");
+  lbpc_status st = check_ready(b);
+  if (st != LBPC_OK) return st;
+  st = enqueue_diag(b, false);
+  if (st != LBPC_OK) return st;
+  const int64_t t0 = b->step;
+  b->cur = 1 - b->cur;
+  b->fresh = 0;
+  b->phi_valid = 1;
+  b->step += 1;
+  st = run_batch_steps(b, n - 1);
+  BHIP(b, hipEventSynchronize(b->diag_ev), "synchronise");
+  bool bad = false;
+  for (int c = 0; c < b->n; ++c) {
+    fill_diag(&out[c], b->res_host + 8 * (size_t)c, b->cfgs[c].cv, t0,
+              flagged(b, c));
+    bad = bad || out[c].nonfinite;
+  }
+  if (st != LBPC_OK) return st;
+  if (bad) return bfail(b, LBPC_ERR_NUMERIC, BAD_STATE);
+  return LBPC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+lbpc_status run_batch_steps(lbpc_batch* b, int64_t n) {
   while (n > 0) {
     const bool steady = !b->fresh && b->phi_valid;
     if (steady && (b->table_fresh || !b->table_phi_valid)) {
@@ -483,6 +582,10 @@ lbpc_status lbpc_batch_step(lbpc_batch* b, int64_t n) {
   return LBPC_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
 lbpc_status lbpc_batch_get_rho_u_T(lbpc_batch* b, int32_t c, double* rho,
                                    double* ux, double* uy, double* T) {
   if (!b) return bfail(nullptr, LBPC_ERR_ARG, "batch is NULL");
@@ -512,33 +615,15 @@ lbpc_status lbpc_batch_get_rho_u_T(lbpc_batch* b, int32_t c, double* rho,
 lbpc_status lbpc_batch_get_diag(lbpc_batch* b, int32_t c, lbpc_diag* out) {
   if (!b) return bfail(nullptr, LBPC_ERR_ARG, "batch is NULL");
   if (c < 0 || c >= b->n || !out) return bfail(b, LBPC_ERR_ARG, "argument");
-  if (!b->initialised[c]) return bfail(b, LBPC_ERR_STATE, "not initialised");
-  double* scr = static_cast<double*>(at(b, b->L.scratch));
-  StepParams p = case_params(b, c, b->cur);
-  BHIP(b, lbpc::launch_macro(p, b->prec, scr, b->stream), "macro kernels");
-  double* dout = static_cast<double*>(at(b, b->L.diag_out));
-  BHIP(b,
-       lbpc::launch_diag(p, scr, b->cfgs[c].rho_v, b->cfgs[c].rho_l,
-                         static_cast<double*>(at(b, b->L.partial)), dout,
-                         b->stream),
-       "diagnostic kernels");
-  double r[8];
-  BHIP(b,
-       hipMemcpyAsync(r, dout, sizeof(r), hipMemcpyDeviceToHost, b->stream),
-       "copy of the diagnostics");
-  BHIP(b, hipStreamSynchronize(b->stream), "synchronise");
-  std::memset(out, 0, sizeof(*out));
-  out->mass = r[0];
-  out->sum_T = r[1];
-  out->sum_rhocvT = r[2];
-  out->liquid_area = r[3];
-  out->radius = std::sqrt(r[3] / M_PI);
-  out->radius_count = std::sqrt(r[4] / M_PI);
-  out->max_speed = r[5];
-  out->nonfinite = r[6] != 0.0 || !std::isfinite(r[0]) ||
-                   !std::isfinite(r[1]) || flagged(b, c);
-  out->step = b->step;
-  if (flagged(b, c)) return bfail(b, LBPC_ERR_NUMERIC, BAD_STATE);
+  for (int k = 0; k < b->n; ++k)
+    if (!b->initialised[k])
+      return bfail(b, LBPC_ERR_STATE, "not every lattice is initialised");
+  lbpc_status st = enqueue_diag(b, true);
+  if (st != LBPC_OK) return st;
+  BHIP(b, hipEventSynchronize(b->diag_ev), "synchronise");
+  fill_diag(out, b->res_host + 8 * (size_t)c, b->cfgs[c].cv, b->step,
+            flagged(b, c));
+  if (out->nonfinite) return bfail(b, LBPC_ERR_NUMERIC, BAD_STATE);
   return LBPC_OK;
 }
 
@@ -554,7 +639,9 @@ void lbpc_batch_destroy(lbpc_batch* b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->stream);
   drop_graphs(b);
+  if (b->diag_ev) (void)hipEventDestroy(b->diag_ev);
   if (b->bad_host) (void)hipHostFree(b->bad_host);
+  if (b->res_host) (void)hipHostFree(b->res_host);
   delete b;
 }
 

@@ -56,6 +56,8 @@ struct StepParams {
   double inv_Tc, two_over_G, inv_cv, lam_over_cv, sig1, sig2;
   // storage shift (rho_ref, T_ref of the shifted forms)
   double rho_ref, T_ref;
+  // coexistence densities of the liquid-area diagnostic
+  double rho_v, rho_l;
   // state flags
   int fresh;      // 1: the input buffer holds pre-collision f(t) (no pull)
   int phi_valid;  // 0: first step, phi_prev := phi

@@ -15,14 +15,14 @@
 #include "lbpc_device.h"
 
 namespace lbpc {
-hipError_t launch_step(const StepParams& p, int prec, hipStream_t s);
+hipError_t launch_step(const StepParams& p, int prec, hipStream_t s,
+                       double* dpart = nullptr, int nostore = 0);
 hipError_t launch_init(const StepParams& p, int prec, const double* in,
                        hipStream_t s);
 hipError_t launch_macro(const StepParams& p, int prec, double* io,
                         hipStream_t s);
-hipError_t launch_diag(const StepParams& p, const double* io, double rho_v,
-                       double rho_l, double* partial, double* out,
-                       hipStream_t s);
+hipError_t launch_diag_reduce(const double* part, const int* ranges, int lo,
+                              int hi, int nlat, double* out, hipStream_t s);
 hipError_t launch_canon(const StepParams& p, int prec, int which, double* out,
                         hipStream_t s);
 hipError_t launch_load(const StepParams& p, int prec, int which,
@@ -31,10 +31,10 @@ hipError_t launch_phi_out(const StepParams& p, int prec, double* out,
                           hipStream_t s);
 hipError_t launch_phi_in(const StepParams& p, int prec, const double* in,
                          hipStream_t s);
-int diag_blocks(long long N);
 hipError_t launch_step_batch(const StepParams* table, const void* work,
                              int nwork, int parity, int grid, int prec,
-                             int bw, hipStream_t s, bool gen = true);
+                             int bw, hipStream_t s, bool gen = true,
+                             double* dpart = nullptr, int nostore = 0);
 int work_item_bytes();
 }  // namespace lbpc
 
@@ -99,14 +99,15 @@ inline Layout plan(const lbpc_config& c) {
   off += hbytes;
   L.scratch = off;
   off += align_up(5 * N * sizeof(double));
+  // tiles of the narrowest strips (60 columns) and shortest runs (4 rows):
+  // the most any tile shape makes, each with one diagnostic record
+  L.work_capacity = (size_t)((c.nx + 59) / 60) * (size_t)((c.ny + 3) / 4);
   L.partial = off;
-  off += align_up((size_t)lbpc::diag_blocks((long long)N) * 8 * sizeof(double));
+  off += align_up(L.work_capacity * 8 * sizeof(double));
   L.diag_out = off;
   off += align_up(8 * sizeof(double));
   L.table = off;
   off += align_up(2 * sizeof(StepParams));
-  // tiles of the narrowest strips (60 columns) and shortest runs (4 rows)
-  L.work_capacity = (size_t)((c.nx + 59) / 60) * (size_t)((c.ny + 3) / 4);
   L.work = off;
   off += align_up(L.work_capacity * 16);
   L.tune_phi = off;
@@ -238,6 +239,8 @@ inline void derive_params(const lbpc_config& c, StepParams& p) {
   }
   p.rho_ref = c.rho_ref;
   p.T_ref = c.T_ref;
+  p.rho_v = c.rho_v;
+  p.rho_l = c.rho_l;
   p.N = (long long)c.nx * c.ny;
 }
 
@@ -259,6 +262,27 @@ inline const char* check_fields(const lbpc_config& c, const double* rho,
   }
   *rho_ave = sum / (double)N;
   return nullptr;
+}
+
+// Fills a diagnostic record from the 8 reduced values (sum rho, sum T,
+// sum rho T, liquid area, count, sum S0, max |v|^2, non-finite) of the time
+// level `step`.
+inline void fill_diag(lbpc_diag* out, const double* r, double cv,
+                      int64_t step, bool flagged) {
+  std::memset(out, 0, sizeof(*out));
+  out->mass = r[0];
+  out->sum_T = r[1];
+  out->sum_rhocvT = cv * r[2];
+  out->liquid_area = r[3];
+  out->radius = std::sqrt(r[3] / M_PI);
+  out->radius_count = std::sqrt(r[4] / M_PI);
+  out->sum_S0 = r[5];
+  out->max_speed = std::sqrt(r[6]);
+  out->step = step;
+  out->nonfinite = (r[7] != 0.0 || !std::isfinite(r[0]) ||
+                    !std::isfinite(r[1]) || !std::isfinite(r[5]) || flagged)
+                       ? 1
+                       : 0;
 }
 
 // Order tiles for the XCDs: workgroup w runs on XCD w % 8, so item w gets
@@ -346,14 +370,16 @@ inline bool edge_strip(const StepParams& p, int bx) {
   return !p.perx && (bx == 0 || bx == p.nbx - 1);
 }
 
-// The tiles of one lattice as (0, bx, by, 0), row of runs by row of runs.
+// The tiles of one lattice as (0, bx, by, slot), row of runs by row of runs;
+// slot numbers them in this order (their diagnostic records).
 inline std::vector<std::array<int, 4>> tile_list(const StepParams& p) {
   const int ni = (p.ny + p.H - 1) / p.H, ne = (p.ny + p.He - 1) / p.He;
   const int nmax = ni > ne ? ni : ne;
   std::vector<std::array<int, 4>> t;
   for (int by = 0; by < nmax; ++by)
     for (int bx = 0; bx < p.nbx; ++bx)
-      if (by < (edge_strip(p, bx) ? ne : ni)) t.push_back({0, bx, by, 0});
+      if (by < (edge_strip(p, bx) ? ne : ni))
+        t.push_back({0, bx, by, (int)t.size()});
   return t;
 }
 

@@ -1,5 +1,6 @@
 // lbpc_probe.hip -- memory-ceiling probes for the benchmark (not part of the
-// step library): what the HBM delivers to (a) a plain device copy and (b) a
+// step library): what the HBM delivers to (a) streaming copy, read-only and
+// write-only kernels and (b) a
 // kernel with exactly the fused step's access pattern and no arithmetic, a
 // pure pull-stream f_a(x) = f*_a(x - e_a) of both distributions plus the
 // phi history, in the same [ny][9][nx] row layout, tile shape, alternating
@@ -12,31 +13,94 @@
 namespace {
 
 template <class T> using Gbl = __attribute__((address_space(1))) T;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ long long pix(int nx, int a, long long y, int x) {
   return (y * 9 + a) * nx + x;
 }
 
-// Plain copy: 16-byte vectors, grid-stride.
-__global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src,
-                                              uint4* __restrict__ dst,
+// Streaming kernels over 16-byte vectors: each thread moves UNR vectors per
+// pass (all loads issued before the first store), grid-stride.  NT selects
+// non-temporal accesses.
+template <int UNR, bool NT>
+__global__ __launch_bounds__(256) void k_copy(const u32x4* __restrict__ src,
+                                              u32x4* __restrict__ dst,
                                               long long n) {
-  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n;
-       i += (long long)gridDim.x * 256)
-    dst[i] = src[i];
+  const long long step = (long long)gridDim.x * 256 * UNR;
+  for (long long base = (long long)blockIdx.x * 256 * UNR + threadIdx.x;
+       base < n; base += step) {
+    u32x4 v[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const long long i = base + (long long)u * 256;
+      if (i < n) v[u] = NT ? __builtin_nontemporal_load(&src[i]) : src[i];
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const long long i = base + (long long)u * 256;
+      if (i < n) {
+        if (NT)
+          __builtin_nontemporal_store(v[u], &dst[i]);
+        else
+          dst[i] = v[u];
+      }
+    }
+  }
+}
+
+// Read only: the vectors' xor, one 16-byte result per thread (kept so the
+// loads are not removed).
+template <int UNR>
+__global__ __launch_bounds__(256) void k_read(const u32x4* __restrict__ src,
+                                              u32x4* __restrict__ out,
+                                              long long n) {
+  u32x4 acc = {0u, 0u, 0u, 0u};
+  const long long step = (long long)gridDim.x * 256 * UNR;
+  for (long long base = (long long)blockIdx.x * 256 * UNR + threadIdx.x;
+       base < n; base += step) {
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const long long i = base + (long long)u * 256;
+      if (i < n) {
+        const u32x4 v = src[i];
+        acc ^= v;
+      }
+    }
+  }
+  out[(long long)blockIdx.x * 256 + threadIdx.x] = acc;
+}
+
+// Write only.
+template <int UNR>
+__global__ __launch_bounds__(256) void k_write(u32x4* __restrict__ dst,
+                                               long long n) {
+  const u32x4 v = {1u, 2u, 3u, 4u};
+  const long long step = (long long)gridDim.x * 256 * UNR;
+  for (long long base = (long long)blockIdx.x * 256 * UNR + threadIdx.x;
+       base < n; base += step) {
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const long long i = base + (long long)u * 256;
+      if (i < n) dst[i] = v;
+    }
+  }
 }
 
 // Pull-stream with the step's tiling: block of BW threads on a strip of W
 // columns (plus 2 halo columns each side) and a run of H rows of a periodic
 // nx x ny lattice; the block marches H + 4 rows (2 halo rows each end) in
 // the direction alternating with the run index, loads all 18 pulled values
-// of every lane and stores those of its own nodes, with the next row's loads
-// issued before the current row's stores.
+// of every lane, with the next row's loads issued before the current row's
+// stores.  Every lane stores every row, so the stores never sit in a branch
+// (a branch around them leaves the compiler's wait counts conservative, and
+// each row would then wait for the one in flight): lanes and rows outside
+// the tile store into a small sink of 19 nx values, which stays in cache.
 template <class T, int BW>
 __global__ __launch_bounds__(BW) void k_pattern(
     const T* __restrict__ fin, const T* __restrict__ gin,
     T* __restrict__ fout, T* __restrict__ gout, const T* __restrict__ phin,
-    T* __restrict__ phout, int nx, int ny, int W, int H, int nbx) {
+    T* __restrict__ phout, T* __restrict__ sink, int nx, int ny, int W,
+    int H, int nbx) {
   const Gbl<T>* F = (const Gbl<T>*)fin;
   const Gbl<T>* G = (const Gbl<T>*)gin;
   Gbl<T>* FO = (Gbl<T>*)fout;
@@ -64,7 +128,10 @@ __global__ __launch_bounds__(BW) void k_pattern(
   const int nit = Y1 - Y0 + 4;
   const int rfirst = dir > 0 ? Y0 - 2 : Y1 + 1;
   auto wrap = [&](int r) { return r < 0 ? r + ny : (r >= ny ? r - ny : r); };
-  auto pull = [&](int r, T* f, T* g) {
+  // the 18 pulled values and the node's phi history of row r, issued
+  // together by every lane (loads complete in order, so a value loaded
+  // after the next row's pull would make its use wait for that whole pull)
+  auto pull = [&](int r, T* f, T* g, T& ph) {
     const int y = wrap(r), ym = wrap(r - 1), yp = wrap(r + 1);
     const int ys[9] = {y, y, ym, y, yp, ym, ym, yp, yp};
     const int xs[9] = {c, xm, c, xp, c, xm, xp, xp, xm};
@@ -73,27 +140,30 @@ __global__ __launch_bounds__(BW) void k_pattern(
       f[a] = F[pix(nx, a, ys[a], xs[a])];
       g[a] = G[pix(nx, a, ys[a], xs[a])];
     }
+    ph = PI[(long long)y * nx + c];
   };
-  auto store = [&](int r, const T* f, const T* g) {
-    if (own && r >= Y0 && r < Y1) {
-      const long long o = (long long)r * nx + c;
-      const T ph = PI[o];
+  Gbl<T>* SK = (Gbl<T>*)sink;
+  auto store = [&](int r, const T* f, const T* g, T ph) {
+    const bool real = own && r >= Y0 && r < Y1;
+    const long long rr = real ? r : 0;
+    Gbl<T>* fo = real ? FO : SK;
+    Gbl<T>* go = real ? GO : SK + 9 * (long long)nx;
+    Gbl<T>* po = real ? PO : SK + 18 * (long long)nx;
 #pragma unroll
-      for (int a = 0; a < 9; ++a) {
-        FO[pix(nx, a, r, c)] = f[a];
-        GO[pix(nx, a, r, c)] = g[a];
-      }
-      PO[o] = ph;
+    for (int a = 0; a < 9; ++a) {
+      fo[pix(nx, a, rr, c)] = f[a];
+      go[pix(nx, a, rr, c)] = g[a];
     }
+    po[rr * nx + c] = ph;
   };
-  T f0[9], g0[9], f1[9], g1[9];
-  pull(rfirst, f0, g0);
+  T f0[9], g0[9], f1[9], g1[9], p0, p1;
+  pull(rfirst, f0, g0, p0);
   for (int it = 0; it < nit; it += 2) {
     const int r = rfirst + dir * it;
-    pull(r + dir, f1, g1);   // row r + 1 in flight while row r is stored
-    store(r, f0, g0);
-    pull(r + 2 * dir, f0, g0);
-    store(r + dir, f1, g1);
+    pull(r + dir, f1, g1, p1);   // row r + 1 in flight while row r is stored
+    store(r, f0, g0, p0);
+    pull(r + 2 * dir, f0, g0, p0);
+    store(r + dir, f1, g1, p1);
   }
 }
 
@@ -101,23 +171,36 @@ __global__ __launch_bounds__(BW) void k_pattern(
 
 extern "C" {
 
-// Copies `bytes` (a multiple of 16) from src to dst on `stream`.
-int lbpc_probe_copy(const void* src, void* dst, size_t bytes, void* stream) {
+// Streaming probes over `bytes` (a multiple of 16) on `stream`, with
+// `blocks` blocks of 256 threads (grid-stride): kind 0 copies src to dst,
+// 1 the same with non-temporal accesses, 2 reads src only (dst receives
+// blocks x 256 x 16 bytes), 3 writes dst only.  Returns 0, -1 for an unknown
+// kind, -2 when the launch fails.
+int lbpc_probe_stream(int kind, const void* src, void* dst, size_t bytes,
+                      int blocks, void* stream) {
   const long long n = (long long)(bytes / 16);
-  hipLaunchKernelGGL(k_copy, dim3(8192), dim3(256), 0, (hipStream_t)stream,
-                     (const uint4*)src, (uint4*)dst, n);
+  hipStream_t s = (hipStream_t)stream;
+  const u32x4* a = (const u32x4*)src;
+  u32x4* b = (u32x4*)dst;
+  switch (kind) {
+    case 0: hipLaunchKernelGGL((k_copy<4, false>), dim3(blocks), dim3(256), 0, s, a, b, n); break;
+    case 1: hipLaunchKernelGGL((k_copy<4, true>), dim3(blocks), dim3(256), 0, s, a, b, n); break;
+    case 2: hipLaunchKernelGGL((k_read<4>), dim3(blocks), dim3(256), 0, s, a, b, n); break;
+    case 3: hipLaunchKernelGGL((k_write<4>), dim3(blocks), dim3(256), 0, s, b, n); break;
+    default: return -1;
+  }
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 // One pull-stream pass of the step's access pattern over a periodic nx x ny
 // lattice (nx, ny >= 16): fin/gin/fout/gout hold 9 nx ny values of
 // elem_bytes (8 or 4) in [ny][9][nx] rows, phin/phout nx ny values of the
-// same type.  Block of bw (256 or 512) threads, strips of W <= bw - 4
+// same type, sink 19 nx values.  Block of bw (256 or 512) threads, strips of W <= bw - 4
 // columns, runs of H rows.  Returns 0, -1 for unsupported arguments, -2 when
 // the launch fails.
 int lbpc_probe_pattern(const void* fin, const void* gin, void* fout,
-                       void* gout, const void* phin, void* phout, int nx,
-                       int ny, int elem_bytes, int bw, int W, int H,
+                       void* gout, const void* phin, void* phout, void* sink,
+                       int nx, int ny, int elem_bytes, int bw, int W, int H,
                        void* stream) {
   // rows up to 5 beyond a run are pulled (wrapped once): ny >= 16
   if (nx < 16 || ny < 16 || W < 1 || W > bw - 4 || H < 1) return -1;
@@ -127,7 +210,7 @@ int lbpc_probe_pattern(const void* fin, const void* gin, void* fout,
 #define LBPC_PROBE(T, BW)                                                      \
   hipLaunchKernelGGL((k_pattern<T, BW>), grid, dim3(BW), 0, s, (const T*)fin,  \
                      (const T*)gin, (T*)fout, (T*)gout, (const T*)phin,        \
-                     (T*)phout, nx, ny, W, H, nbx)
+                     (T*)phout, (T*)sink, nx, ny, W, H, nbx)
   if (elem_bytes == 8 && bw == 512) LBPC_PROBE(double, 512);
   else if (elem_bytes == 8 && bw == 256) LBPC_PROBE(double, 256);
   else if (elem_bytes == 4 && bw == 512) LBPC_PROBE(float, 512);

@@ -3,17 +3,19 @@
 // One launch performs one whole time step (pull-streaming, moments, EOS,
 // force, velocity, thermal source, both MRT collisions, store).  Layout and
 // schedule:
-//   * distributions are SoA [9][ny][nx] per buffer, ping-pong; the kernel
-//     reads post-collision f*(t-1), g*(t-1) (or pre-collision f(t), g(t)
-//     right after an initialisation: "fresh") and writes f*(t), g*(t);
-//   * a block of 256 threads (4 wave64) owns a strip of W = 252 columns plus
-//     2 halo columns per side (one column per thread) and a run of H rows;
-//     it marches up the rows.  Iteration r:
+//   * each distribution buffer interleaves the rows of its nine direction
+//     arrays, [ny][9][nx]; two buffers per distribution, ping-pong.  The
+//     kernel reads post-collision f*(t-1), g*(t-1) (or pre-collision f(t),
+//     g(t) right after an initialisation: "fresh") and writes f*(t), g*(t);
+//   * a block of BLOCK threads (64 to 512: one to eight wave64) owns a strip
+//     of at most BLOCK - 4 columns plus 2 halo columns per side (one column
+//     per thread) and a run of H rows, and marches along the rows (up or
+//     down, alternating between vertically adjacent runs).  Iteration r:
 //       A(r)   rho, j, T of row r from its pulled f, g; EOS (FP64): psi and
-//              T (dp/dT)_rho -> LDS ring (5 rows) / registers
+//              T (dp/dT)_rho -> LDS rings (5 rows) / registers
 //       B(r-1) interaction force from psi rows r-2..r, buoyancy, velocity
 //              -> LDS ring; flow MRT collision of row r-1, store f*
-//       pull of row r+1 issued here, in flight during C2
+//       pull of the next row(s) issued here, in flight during C2
 //       C(r-2) isotropic differences of T, v (and rho) on rows r-3..r-1,
 //              thermal source phi, S0, improved thermal MRT collision of
 //              row r-2 (or a BGK collision: the Gong-Cheng model, or the
@@ -22,7 +24,16 @@
 //     columns and the 4 warm-up rows aside) and the 2-hop stencil dependence
 //     (div v needs v one node away, which needs psi two nodes away) never
 //     goes to memory;
-//   * pulled f is held in registers for one row, pulled g for two.
+//   * pulled values wait as loaded (register images) until used: FP64 pulls
+//     one row ahead and holds f one row and g two rows in registers; the
+//     4- and 2-byte storage forms pull two rows ahead and keep cooked g of
+//     the rows waiting for C in a per-thread LDS ring;
+//   * a diagnostic launch (DIAG) also sums, in FP64, the fields of the time
+//     level it starts from over the block's own nodes (at C, where rho, T
+//     and v of the node are at hand) and reduces them across the wave
+//     (butterfly shuffles), then across the block, into one record per
+//     tile; a no-store diagnostic launch computes the same without storing
+//     anything (the state stays as it is).
 // Non-periodic sides: the pull applies bounce-back / open rules at edge
 // nodes, and LDS reads of a ghost neighbour take the nearest lattice node's
 // values with the ghost temperature / velocity rule.
@@ -63,8 +74,14 @@ template <int P> struct StepOcc {
 
 // One tile: strip bx (W columns + halo), row run by (H rows), of the lattice
 // described by p.
-template <int P, bool GEN, int BLOCK>
-__device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
+// Diagnostic record of a tile, 8 FP64 values: sum rho, sum T, sum rho T,
+// liquid area, count above the mid density, sum S0, max |v|^2, non-finite.
+constexpr int DIAG_VALS = 8;
+
+template <int P, bool GEN, int BLOCK, bool DIAG>
+__device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
+                                          int slot, double* __restrict__ dpart,
+                                          bool nostore) {
   using Tr = Prec<P>;
   using S = typename Tr::S;
   using C = typename Tr::C;
@@ -179,6 +196,10 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
   }
   __shared__ C s_g[PD == 2 ? 3 : 1][PD == 2 ? Q : 1][PD == 2 ? BLOCK : 1];
   C jx1 = C(0), jy1 = C(0), tdp1 = C(0), tdp2 = C(0), irq = C(0);
+  // diagnostic sums of this thread's own nodes (DIAG only)
+  double d_m = 0.0, d_T = 0.0, d_e = 0.0, d_a = 0.0, d_c = 0.0, d_s = 0.0,
+         d_v = 0.0, d_bad = 0.0;
+  const bool skip = DIAG && nostore;
 
 #pragma unroll
   for (int k = 0; k < PD; ++k) pull_row(rfirst + k * dir, F[k], G[k]);
@@ -317,7 +338,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
         s_vx[sl1][t] = vx;
         s_vy[sl1][t] = vy;
 
-        if (doC && rb >= Y0 && rb < Y1) {
+        if (doC && rb >= Y0 && rb < Y1 && !skip) {
           // flow MRT collision with the forcing scheme of the flow model;
           // |F_m|^2 / psi^2 = G^2 (sx^2 + sy^2), folded into sig1, sig2
           C m[Q], ms[Q], fo[Q], fb[Q];
@@ -501,6 +522,24 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
           const C prev = p.phi_valid ? hphi : phi;
           S0 = phi + C(0.5) * (phi - prev);
         }
+        if constexpr (DIAG) {
+          // FP64 sums of the time level this step starts from
+          const double rd = double(s_rho[sl2][t]);
+          const double Td = double(T), vxd = double(vx), vyd = double(vy);
+          d_m += rd;
+          d_T += Td;
+          d_e += rd * Td;
+          double fr = (rd - p.rho_v) / (p.rho_l - p.rho_v);
+          fr = fr < 0.0 ? 0.0 : (fr > 1.0 ? 1.0 : fr);
+          d_a += fr;
+          d_c += rd > 0.5 * (p.rho_l + p.rho_v) ? 1.0 : 0.0;
+          d_s += double(S0);
+          const double sp = vxd * vxd + vyd * vyd;
+          d_v = sp > d_v ? sp : d_v;
+          if (!(rd - rd == 0.0 && Td - Td == 0.0 && sp - sp == 0.0))
+            d_bad = 1.0;
+        }
+        if (!skip) {
         phio[o] = phi;
         C go[Q], gb[Q];
         if constexpr (PD == 1) {
@@ -566,6 +605,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
 #pragma unroll
         for (int a = 0; a < Q; ++a)
           Tr::st(gout, dix(nx, a, yc, c), go[a] - sh.g(a));
+        }  // !skip
       }
     }
 
@@ -599,6 +639,36 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by) {
       iteration(std::integral_constant<int, 2>{}, it + 2);
     }
   }
+
+  if constexpr (DIAG) {
+    // butterfly over the wave (every lane ends with the wave's total; lane 0
+    // keeps it), then the waves in order: a fixed order, so the record is
+    // the same on every run
+    __shared__ double s_red[BLOCK / 64][DIAG_VALS];
+    double v[DIAG_VALS] = {d_m, d_T, d_e, d_a, d_c, d_s, d_v, d_bad};
+#pragma unroll
+    for (int k = 0; k < DIAG_VALS; ++k) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v[k], off, 64);
+        v[k] = k >= 6 ? (o > v[k] ? o : v[k]) : v[k] + o;
+      }
+    }
+    if ((t & 63) == 0) {
+#pragma unroll
+      for (int k = 0; k < DIAG_VALS; ++k) s_red[t >> 6][k] = v[k];
+    }
+    __syncthreads();
+    if (t < DIAG_VALS) {
+      double acc = s_red[0][t];
+#pragma unroll
+      for (int w = 1; w < BLOCK / 64; ++w) {
+        const double o = s_red[w][t];
+        acc = t >= 6 ? (o > acc ? o : acc) : acc + o;
+      }
+      dpart[(long long)slot * DIAG_VALS + t] = acc;
+    }
+  }
 }
 
 // Waves per SIMD a block shape can reach: a 512-thread block (8 waves) with
@@ -608,46 +678,57 @@ template <int P, int BLOCK> struct BlockOcc {
   static constexpr int waves = BLOCK == 512 ? 2 : StepOcc<P>::waves;
 };
 
-template <int P, bool GEN, int BLOCK>
+template <int P, bool GEN, int BLOCK, bool DIAG>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(
     BlockOcc<P, BLOCK>::waves, BlockOcc<P, BLOCK>::waves))) void
-k_step(StepParams p) {
+k_step(StepParams p, double* dpart, int nostore) {
   int bx, by;
   block_tile(p, bx, by);
-  step_tile<P, GEN, BLOCK>(p, bx, by);
+  step_tile<P, GEN, BLOCK, DIAG>(p, bx, by, by * p.nbx + bx, dpart,
+                                 nostore != 0);
 }
 
 // Batched form: many independent lattices, one persistent launch per step.
 // `table` holds each case's parameters for both buffer parities; `work`
-// lists (case, bx, by) tiles, costliest first; every block walks the list
-// with a stride of the grid size, so each tile is done exactly once and
-// every block leaves when the list ends.
+// lists (case, bx, by, slot) tiles, costliest first (slot: the tile's
+// diagnostic record; the records of one lattice are contiguous); every
+// block walks the list with a stride of the grid size, so each tile is done
+// exactly once and every block leaves when the list ends.
 struct WorkItem {
-  int c, bx, by, pad;
+  int c, bx, by, slot;
 };
 
-template <int P, int BLOCK, bool GEN>
+template <int P, int BLOCK, bool GEN, bool DIAG>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(
     BlockOcc<P, BLOCK>::waves, BlockOcc<P, BLOCK>::waves))) void
 k_step_batch(const StepParams* __restrict__ table,
-             const WorkItem* __restrict__ work, int nwork, int parity) {
+             const WorkItem* __restrict__ work, int nwork, int parity,
+             double* dpart, int nostore) {
   for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
     const WorkItem it = work[w];
     const StepParams& p = table[2 * it.c + parity];
-    step_tile<P, GEN, BLOCK>(p, it.bx, it.by);
+    step_tile<P, GEN, BLOCK, DIAG>(p, it.bx, it.by, it.slot, dpart,
+                                   nostore != 0);
     __syncthreads();  // the LDS rings are reused by the next tile
   }
 }
 
-// host-side launcher: one instantiation per storage precision and boundary
-// mode (GEN = some side is not periodic)
-hipError_t launch_step(const StepParams& p, int prec, hipStream_t s) {
+// host-side launchers: one instantiation per storage precision, block
+// width, boundary mode (GEN = some side is not periodic) and diagnostic mode
+// (dpart != nullptr: sum the diagnostics into dpart; nostore: store nothing)
+hipError_t launch_step(const StepParams& p, int prec, hipStream_t s,
+                       double* dpart, int nostore) {
   const dim3 grid(p.nbx * p.nby);
   const bool gen = !(p.perx && p.pery);
-  // lattices with a non-periodic side run the persistent tile kernel
+  // lattices with a non-periodic side run the tile-list kernel
   if (gen) return hipErrorInvalidValue;
 #define LBPC_LAUNCH_BW(PR, BW)                                              \
-  hipLaunchKernelGGL((k_step<PR, false, BW>), grid, dim3(BW), 0, s, p);
+  if (dpart)                                                                \
+    hipLaunchKernelGGL((k_step<PR, false, BW, true>), grid, dim3(BW), 0, s, \
+                       p, dpart, nostore);                                  \
+  else                                                                      \
+    hipLaunchKernelGGL((k_step<PR, false, BW, false>), grid, dim3(BW), 0,   \
+                       s, p, dpart, 0);
 #define LBPC_LAUNCH(PR)                                                     \
   if (p.bw == 64) {                                                         \
     LBPC_LAUNCH_BW(PR, 64)                                                  \
@@ -672,15 +753,26 @@ hipError_t launch_step(const StepParams& p, int prec, hipStream_t s) {
 
 hipError_t launch_step_batch(const StepParams* table, const void* work,
                              int nwork, int parity, int grid, int prec,
-                             int bw, hipStream_t s, bool gen) {
+                             int bw, hipStream_t s, bool gen, double* dpart,
+                             int nostore) {
   const WorkItem* wk = static_cast<const WorkItem*>(work);
-#define LBPC_BLAUNCH_BW(PR, BW)                                               \
-  if (gen)                                                                    \
-    hipLaunchKernelGGL((k_step_batch<PR, BW, true>), dim3(grid), dim3(BW), 0, \
-                       s, table, wk, nwork, parity);                          \
-  else                                                                        \
-    hipLaunchKernelGGL((k_step_batch<PR, BW, false>), dim3(grid), dim3(BW),   \
-                       0, s, table, wk, nwork, parity);
+#define LBPC_BL(PR, BW, G, D)                                                \
+  hipLaunchKernelGGL((k_step_batch<PR, BW, G, D>), dim3(grid), dim3(BW), 0, \
+                     s, table, wk, nwork, parity, dpart, nostore);
+#define LBPC_BLAUNCH_BW(PR, BW)                                              \
+  if (gen) {                                                                 \
+    if (dpart) {                                                             \
+      LBPC_BL(PR, BW, true, true)                                            \
+    } else {                                                                 \
+      LBPC_BL(PR, BW, true, false)                                           \
+    }                                                                        \
+  } else {                                                                   \
+    if (dpart) {                                                             \
+      LBPC_BL(PR, BW, false, true)                                           \
+    } else {                                                                 \
+      LBPC_BL(PR, BW, false, false)                                          \
+    }                                                                        \
+  }
 #define LBPC_BLAUNCH(PR)                                                      \
   if (bw == 64) {                                                             \
     LBPC_BLAUNCH_BW(PR, 64)                                                   \
@@ -700,6 +792,7 @@ hipError_t launch_step_batch(const StepParams* table, const void* work,
   }
 #undef LBPC_BLAUNCH
 #undef LBPC_BLAUNCH_BW
+#undef LBPC_BL
   return hipGetLastError();
 }
 

@@ -23,11 +23,12 @@ FP64, FP32, FP32_SHIFTED, FP16_SHIFTED = 0, 1, 2, 3
 # every entry point declared in include/lbpc.h
 EXPORTS = (
     "lbpc_workspace_bytes", "lbpc_create", "lbpc_init_fields", "lbpc_step",
-    "lbpc_get_rho_u_T", "lbpc_get_diag", "lbpc_state_bytes",
+    "lbpc_get_rho_u_T", "lbpc_get_diag", "lbpc_step_diag", "lbpc_state_bytes",
     "lbpc_save_state", "lbpc_load_state", "lbpc_destroy", "lbpc_last_error",
     "lbpc_set_tiles", "lbpc_get_tiles", "lbpc_autotune", "lbpc_batch_workspace_bytes", "lbpc_batch_create",
     "lbpc_batch_init_fields", "lbpc_batch_set_tiles", "lbpc_batch_autotune",
-    "lbpc_batch_step", "lbpc_batch_get_rho_u_T", "lbpc_batch_get_diag",
+    "lbpc_batch_step", "lbpc_batch_step_diag", "lbpc_batch_get_rho_u_T",
+    "lbpc_batch_get_diag",
     "lbpc_batch_nodes", "lbpc_batch_destroy", "lbpc_batch_last_error",
 )
 
@@ -61,7 +62,6 @@ class Diag(ctypes.Structure):
         ("sum_rhocvT", ctypes.c_double), ("liquid_area", ctypes.c_double),
         ("radius", ctypes.c_double), ("radius_count", ctypes.c_double),
         ("max_speed", ctypes.c_double), ("sum_S0", ctypes.c_double),
-        ("sum_Fx", ctypes.c_double), ("sum_Fy", ctypes.c_double),
         ("step", ctypes.c_int64), ("nonfinite", ctypes.c_int32),
         ("pad", ctypes.c_int32),
     ]
@@ -94,6 +94,7 @@ def lib():
         L.lbpc_step.argtypes = [vp, ctypes.c_int64]
         L.lbpc_get_rho_u_T.argtypes = [vp, dp, dp, dp, dp]
         L.lbpc_get_diag.argtypes = [vp, ctypes.POINTER(Diag)]
+        L.lbpc_step_diag.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(Diag)]
         L.lbpc_state_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
         L.lbpc_save_state.argtypes = [vp, vp, ctypes.c_size_t]
         L.lbpc_load_state.argtypes = [vp, vp, ctypes.c_size_t]
@@ -117,6 +118,8 @@ def lib():
         L.lbpc_batch_autotune.argtypes = [vp, i32, ctypes.POINTER(i32),
                                           ctypes.POINTER(i32), dp]
         L.lbpc_batch_step.argtypes = [vp, ctypes.c_int64]
+        L.lbpc_batch_step_diag.argtypes = [vp, ctypes.c_int64,
+                                           ctypes.POINTER(Diag)]
         L.lbpc_batch_get_rho_u_T.argtypes = [vp, i32, dp, dp, dp, dp]
         L.lbpc_batch_get_diag.argtypes = [vp, i32, ctypes.POINTER(Diag)]
         L.lbpc_batch_nodes.argtypes = [vp, i64p]
@@ -191,10 +194,20 @@ def lbpc_get_rho_u_T(h, shape):
     return tuple(out)
 
 
+def _diag_dict(d) -> dict:
+    return {n: getattr(d, n) for n, _ in Diag._fields_ if n != "pad"}
+
+
 def lbpc_get_diag(h) -> dict:
     d = Diag()
     _check(lib().lbpc_get_diag(h, ctypes.byref(d)), h)
-    return {n: getattr(d, n) for n, _ in Diag._fields_ if n != "pad"}
+    return _diag_dict(d)
+
+
+def lbpc_step_diag(h, n: int) -> dict:
+    d = Diag()
+    _check(lib().lbpc_step_diag(h, int(n), ctypes.byref(d)), h)
+    return _diag_dict(d)
 
 
 def lbpc_save_state(h) -> np.ndarray:
@@ -301,17 +314,26 @@ class Simulation:
         with self._on():
             return lbpc_get_diag(self.h)
 
+    def step_diag(self, n: int = 1) -> dict:
+        """n steps; the diagnostics of the level they start from, reduced
+        inside the first of them."""
+        with self._on():
+            return lbpc_step_diag(self.h, n)
+
     def run(self, steps: int, every: int, log=None) -> list:
         """Advances `steps` steps, taking the FP64 diagnostics after every
         `every` steps (and after the last); returns the records and appends
-        each as one JSON line to `log` (a path or text file) if given."""
+        each as one JSON line to `log` (a path or text file) if given.  The
+        records of the levels a later step starts from are reduced inside
+        that step; the last level's by a no-store pass."""
         out = []
-        done = 0
+        done = min(every, steps)
+        self.step(done)
         while done < steps:
             k = min(every, steps - done)
-            self.step(k)
+            out.append(self.step_diag(k))
             done += k
-            out.append(self.diag())
+        out.append(self.diag())
         _log_records(log, out)
         return out
 
@@ -434,7 +456,15 @@ class Batch:
         with self._on():
             _bcheck(lib().lbpc_batch_get_diag(self.h, int(c),
                                               ctypes.byref(d)), self.h)
-        return {n: getattr(d, n) for n, _ in Diag._fields_ if n != "pad"}
+        return _diag_dict(d)
+
+    def step_diag(self, n: int = 1) -> list:
+        """n steps of every lattice; each lattice's diagnostics of the level
+        they start from, reduced inside the first of them."""
+        arr = (Diag * len(self.cfgs))()
+        with self._on():
+            _bcheck(lib().lbpc_batch_step_diag(self.h, int(n), arr), self.h)
+        return [_diag_dict(d) for d in arr]
 
     def run(self, steps: int, every: int, log=None) -> list:
         """Advances every lattice `steps` steps, taking each lattice's FP64
@@ -442,13 +472,14 @@ class Batch:
         the records (each with its lattice index) and appends them as JSON
         lines to `log` if given."""
         out = []
-        done = 0
+        done = min(every, steps)
+        self.step(done)
         while done < steps:
             k = min(every, steps - done)
-            self.step(k)
+            out += [dict(d, lattice=c)
+                    for c, d in enumerate(self.step_diag(k))]
             done += k
-            for c in range(len(self.cfgs)):
-                out.append(dict(self.diag(c), lattice=c))
+        out += [dict(self.diag(c), lattice=c) for c in range(len(self.cfgs))]
         _log_records(log, out)
         return out
 

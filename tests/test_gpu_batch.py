@@ -127,7 +127,16 @@ def test_diag_per_lattice():
         do, db = o.diag(), b.diag(k)
         assert np.isclose(db["mass"], do["mass"], rtol=1e-12)
         assert np.isclose(db["sum_T"], do["sum_T"], rtol=1e-12)
+        assert np.isclose(db["liquid_area"], do["liquid_area"], rtol=1e-11)
+        assert np.isclose(db["max_speed"], do["max_speed"], rtol=1e-10)
         assert db["step"] == 50
+    # the diagnostic step gives every lattice's record of the same level,
+    # bitwise the no-store pass's (same kernel, same reduction order)
+    before = [b.diag(k) for k in range(len(cases))]
+    recs = b.step_diag(2)
+    assert recs == before
+    for k in range(len(cases)):
+        assert recs[k]["step"] == 50 and b.diag(k)["step"] == 52
     b.close()
 
 

@@ -97,7 +97,10 @@ def test_impossible_density_is_flagged_like_the_oracle():
 
 def test_runaway_flow_fails_on_the_same_step_as_the_oracle():
     """A droplet in a uniform flow u = 0.5 leaves the scheme's range: the
-    first step that meets an invalid state is the same on both sides."""
+    first invalid time level is the same on both sides.  The oracle stops at
+    the start of the step from that level; on the GPU the diagnostic pass of
+    that level reports it (it checks the level's node states as a step
+    does), and the step from it is refused."""
     cfg, fl = I.static_droplet(32, 32, 8.0)
     fl["ux"] = np.full((32, 32), 0.5)
     o = O.Oracle(cfg)
@@ -110,15 +113,18 @@ def test_runaway_flow_fails_on_the_same_step_as_the_oracle():
             o_fail = s
             break
     assert o_fail is not None
+    assert o.diag()["nonfinite"] == 1      # the level the oracle stopped at
     g = _sim(cfg, fl)
-    g_fail = None
+    g_bad = None
     for s in range(1, 60):
         g.step(1)
         if _status(g.diag) == NUMERIC:
-            g_fail = s
+            g_bad = s
             break
+    refused = _status(lambda: g.step(1))
     g.close()
-    assert g_fail == o_fail, (g_fail, o_fail)
+    assert g_bad == o_fail - 1, (g_bad, o_fail)
+    assert refused == NUMERIC
 
 
 def test_batch_flags_only_the_failing_lattice():

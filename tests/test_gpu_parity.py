@@ -140,8 +140,22 @@ def test_save_load_roundtrip_matches_uninterrupted():
     g2.close()
 
 
-def test_diag_matches_oracle():
-    cfg, fl = I.evaporation(96, 20.0, 1.1)
+DIAG_KEYS = ("mass", "sum_T", "sum_rhocvT", "liquid_area", "radius",
+             "max_speed")
+
+
+@pytest.mark.parametrize("case", ["open", "walls_tiled", "bgk"])
+def test_diag_matches_oracle(case):
+    """The no-store diagnostic pass (lbpc_get_diag) and the diagnostic step
+    (lbpc_step_diag) against the oracle's sums at the same level; sum S0 of
+    the step from a level is the oracle's S0 sum of that step."""
+    if case == "open":
+        cfg, fl = I.evaporation(96, 20.0, 1.1)
+    elif case == "walls_tiled":
+        cfg, fl = I.bubble(nx=96, ny=80, pool=50, hot_width=10, g=3e-5)
+    else:
+        cfg, fl = I.static_droplet(72, 64, 15.0)
+        cfg.update(thermal_model=I.THERMAL_IMPROVED_BGK, gy=-2e-5)
     o = O.Oracle(cfg)
     o.init_fields(**fl)
     g = _gpu().Simulation(cfg)
@@ -149,12 +163,40 @@ def test_diag_matches_oracle():
     o.step(100)
     g.step(100)
     do, dg = o.diag(), g.diag()
+    ds = g.step_diag(3)          # level 100, then on to 103
+    o.step(1)
+    do1 = o.diag()               # its sum_S0: the step 100 -> 101
+    o.step(2)
+    dend, gend = o.diag(), g.diag()
     g.close()
-    for k in ("mass", "sum_T", "sum_rhocvT", "liquid_area", "radius",
-              "max_speed"):
+    for k in DIAG_KEYS:
         assert np.isclose(dg[k], do[k], rtol=1e-11, atol=1e-14), k
-    assert dg["radius_count"] == do["radius_count"]
-    assert dg["step"] == 100 and not dg["nonfinite"]
+        assert dg[k] == ds[k], k     # same reduction, same order
+        assert np.isclose(gend[k], dend[k], rtol=1e-11, atol=1e-14), k
+    assert dg["radius_count"] == do["radius_count"] == ds["radius_count"]
+    assert np.isclose(dg["sum_S0"], do1["sum_S0"], rtol=1e-9, atol=1e-15)
+    assert ds["sum_S0"] == dg["sum_S0"]
+    assert dg["step"] == ds["step"] == 100 and gend["step"] == 103
+    assert not dg["nonfinite"] and not ds["nonfinite"]
+
+
+def test_diag_is_deterministic_and_budget_closes():
+    """Two runs give bitwise the same diagnostics; on a periodic lattice
+    sum T of the next level is sum T + sum S0 (Eq. 46: the collision changes
+    the zeroth thermal moment by S0 only, streaming permutes)."""
+    cfg, fl = I.static_droplet(128, 96, 20.0)
+    cfg.update(gy=-1e-5, s_g=[1.0, 1.2, 0.9, 1.1, 1.3, 1.1, 0.8, 1.05, 0.95])
+    runs = []
+    for _ in range(2):
+        g = _gpu().Simulation(cfg)
+        g.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
+        g.step(7)
+        runs.append([g.step_diag(1) for _ in range(4)])
+        g.close()
+    assert runs[0] == runs[1]
+    for a, b in zip(runs[0], runs[0][1:]):
+        assert np.isclose(b["sum_T"], a["sum_T"] + a["sum_S0"], rtol=1e-13,
+                          atol=1e-13)
 
 
 @pytest.mark.parametrize("which", ["periodic", "walls"])
