@@ -248,6 +248,19 @@ lbpc_status lbpc_get_rho_u_T(lbpc_handle *h, double *rho, double *ux,
  * not finite. */
 lbpc_status lbpc_get_diag(lbpc_handle *h, lbpc_diag *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * lbpc_get_diag with its tile records and results in a static device array
+ * of the library instead of the workspace.  The array holds 65536 tile
+ * records (4 MiB with the results); every GPU the library runs on keeps its
+ * own copy until the process ends.  The call allocates nothing and sets no
+ * memory; it returns LBPC_ERR_UNSUPPORTED when the handle's tile shape has
+ * more than 65536 tiles (use taller tiles, or lbpc_get_diag).  Every call on
+ * one GPU uses that GPU's array, so calls that overlap on one GPU (several
+ * threads, or several streams in flight) race; each call waits for its
+ * result before returning.  Same values as lbpc_get_diag (bitwise). */
+lbpc_status lbpc_get_diag_noalloc(lbpc_handle *h, lbpc_diag *out);
+
 /* Enqueues n >= 1 time steps like lbpc_step; the first of them also
  * reduces the diagnostics of the time level it starts from (the current
  * one), on the way, in the same launch.  Returns once that first step's

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <array>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -117,6 +118,38 @@ double* ws_part(lbpc_handle* h) {
 }
 double* ws_dout(lbpc_handle* h) {
   return static_cast<double*>(at(h, h->L.diag_out));
+}
+
+// Scratch of lbpc_get_diag_noalloc, for callers that cannot allocate:
+// NOALLOC_RECORDS tile records of 8 FP64 values, then the 8 results (4 MiB
+// in all), held by every GPU the library runs on until the process ends.
+// In host code `scratch` names a host-side stand-in, not device memory: its
+// device address on the current GPU comes from hipGetSymbolAddress, taken
+// once per device (at the first initialisation on it) and kept below.
+constexpr int NOALLOC_RECORDS = 65536;
+__device__ __align__(256) double scratch[((size_t)NOALLOC_RECORDS + 1) * 8];
+constexpr int MAX_DEVICES = 64;
+double* g_scratch_ptr[MAX_DEVICES];
+std::mutex g_scratch_mu;
+
+// device address of this GPU's scratch (looked up on the current device)
+lbpc_status scratch_for_device(lbpc_handle* h, double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(h, e, "current device");
+  if (dev < 0 || dev >= MAX_DEVICES)
+    return fail(h, LBPC_ERR_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return hip_fail(h, e != hipSuccess ? e : hipErrorInvalidSymbol,
+                      "address of the diagnostic scratch");
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return LBPC_OK;
 }
 
 // step parameters for the current state (input = buffer cur)
@@ -359,6 +392,9 @@ lbpc_status lbpc_init_fields(lbpc_handle* h, const double* rho,
   {
     lbpc_status st = reset_flag(h);
     if (st != LBPC_OK) return st;
+    double* sp = nullptr;  // set-up of lbpc_get_diag_noalloc on this device
+    st = scratch_for_device(h, &sp);
+    if (st != LBPC_OK) return st;
   }
   h->fresh = 1;
   h->phi_valid = 0;
@@ -556,6 +592,25 @@ lbpc_status lbpc_get_diag(lbpc_handle* h, lbpc_diag* out) {
   if (!out) return fail(h, LBPC_ERR_ARG, "out is NULL");
   if (!h->initialised) return fail(h, LBPC_ERR_STATE, "diag before init");
   lbpc_status st = enqueue_diag(h, true, ws_part(h), ws_dout(h));
+  if (st != LBPC_OK) return st;
+  HIP_TRY(h, hipEventSynchronize(h->diag_ev), "synchronise");
+  fill_diag(out, h->res_host, h->cfg.cv, h->step, flagged(h));
+  if (out->nonfinite) return fail(h, LBPC_ERR_NUMERIC, BAD_STATE);
+  return LBPC_OK;
+}
+
+lbpc_status lbpc_get_diag_noalloc(lbpc_handle* h, lbpc_diag* out) {
+  if (!h) return fail(nullptr, LBPC_ERR_ARG, "handle is NULL");
+  if (!out) return fail(h, LBPC_ERR_ARG, "out is NULL");
+  if (!h->initialised) return fail(h, LBPC_ERR_STATE, "diag before init");
+  if (tile_count(h) > NOALLOC_RECORDS)
+    return fail(h, LBPC_ERR_UNSUPPORTED,
+                "more tiles than the static diagnostic scratch holds "
+                "(65536): use lbpc_get_diag or taller tiles");
+  double* base = nullptr;
+  lbpc_status st = scratch_for_device(h, &base);
+  if (st != LBPC_OK) return st;
+  st = enqueue_diag(h, true, base, base + (size_t)NOALLOC_RECORDS * 8);
   if (st != LBPC_OK) return st;
   HIP_TRY(h, hipEventSynchronize(h->diag_ev), "synchronise");
   fill_diag(out, h->res_host, h->cfg.cv, h->step, flagged(h));

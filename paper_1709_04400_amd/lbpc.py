@@ -23,7 +23,8 @@ FP64, FP32, FP32_SHIFTED, FP16_SHIFTED = 0, 1, 2, 3
 # every entry point declared in include/lbpc.h
 EXPORTS = (
     "lbpc_workspace_bytes", "lbpc_create", "lbpc_init_fields", "lbpc_step",
-    "lbpc_get_rho_u_T", "lbpc_get_diag", "lbpc_step_diag", "lbpc_state_bytes",
+    "lbpc_get_rho_u_T", "lbpc_get_diag", "lbpc_get_diag_noalloc",
+    "lbpc_step_diag", "lbpc_state_bytes",
     "lbpc_save_state", "lbpc_load_state", "lbpc_destroy", "lbpc_last_error",
     "lbpc_set_tiles", "lbpc_get_tiles", "lbpc_autotune", "lbpc_batch_workspace_bytes", "lbpc_batch_create",
     "lbpc_batch_init_fields", "lbpc_batch_set_tiles", "lbpc_batch_autotune",
@@ -95,6 +96,7 @@ def lib():
         L.lbpc_get_rho_u_T.argtypes = [vp, dp, dp, dp, dp]
         L.lbpc_get_diag.argtypes = [vp, ctypes.POINTER(Diag)]
         L.lbpc_step_diag.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(Diag)]
+        L.lbpc_get_diag_noalloc.argtypes = [vp, ctypes.POINTER(Diag)]
         L.lbpc_state_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
         L.lbpc_save_state.argtypes = [vp, vp, ctypes.c_size_t]
         L.lbpc_load_state.argtypes = [vp, vp, ctypes.c_size_t]
@@ -201,6 +203,12 @@ def _diag_dict(d) -> dict:
 def lbpc_get_diag(h) -> dict:
     d = Diag()
     _check(lib().lbpc_get_diag(h, ctypes.byref(d)), h)
+    return _diag_dict(d)
+
+
+def lbpc_get_diag_noalloc(h) -> dict:
+    d = Diag()
+    _check(lib().lbpc_get_diag_noalloc(h, ctypes.byref(d)), h)
     return _diag_dict(d)
 
 
@@ -313,6 +321,12 @@ class Simulation:
     def diag(self) -> dict:
         with self._on():
             return lbpc_get_diag(self.h)
+
+    def diag_noalloc(self) -> dict:
+        """lbpc_get_diag_noalloc: the same values, with the library's static
+        scratch instead of the workspace."""
+        with self._on():
+            return lbpc_get_diag_noalloc(self.h)
 
     def step_diag(self, n: int = 1) -> dict:
         """n steps; the diagnostics of the level they start from, reduced
