@@ -355,3 +355,51 @@ def test_max_speed_picks_the_fastest_node():
     ux[8, 1] = 0.05
     d = _diag_of(np.full((n, n), 3.0), ux, uy)
     assert np.isclose(d["max_speed"], 0.1, rtol=1e-13)
+
+
+# ---------------------------------------------------------------- corners --
+# Reading at a corner where an open x side meets a wall y side: the wall
+# wins (a link or neighbour crossing both is a wall one) and the y side
+# gives its temperature.
+
+def _corner_first_step(lam):
+    T0, Tl, Tb = I.T_SAT, 1.07 * I.T_SAT, 1.2 * I.T_SAT
+    n, rho0 = 10, 3.0
+    cfg = I.base_config(n, n, flags=O.FLAG_FREEZE_FLOW, lambda0=lam,
+                        bc=[I.BC_OPEN, I.BC_OPEN, I.BC_WALL, I.BC_WALL],
+                        T_bc=[Tl, T0, Tb, T0])
+    z = np.zeros((n, n))
+    o = _oracle(cfg, np.full((n, n), rho0), z, z, np.full((n, n), T0))
+    o.step(1)
+    return o, rho0, T0, Tl, Tb
+
+
+def test_corner_first_step_temperature():
+    """Uniform T0 at rest, thermal rates 1, lambda = rho c_V k (phi = 0):
+    a wall link adds 2 wg (T_side - T0) and an open link wg (T_side - T0),
+    wg = 1/18.  At the corner node (0, 0): directions 2 and 6 cross the y-
+    wall and 5 crosses both sides, a wall link at the y side's T_b; 1 and 8
+    cross the open x- side at T_l.  So T - T0 = (6 (T_b - T0) + 2 (T_l -
+    T0))/18 there; away from the corners an x- edge node gets 3 (T_l -
+    T0)/18 (open links 1, 5, 8) and a y- edge node 6 (T_b - T0)/18 (wall
+    links 2, 5, 6)."""
+    o, rho0, T0, Tl, Tb = _corner_first_step(3.0 * I.CV * _k())
+    T = o.rho_u_T()[3]
+    assert abs(T[0, 0] - T0 - (6 * (Tb - T0) + 2 * (Tl - T0)) / 18) < 1e-15
+    # an x- edge node away from the corners: open links 1, 5, 8
+    assert abs(T[4, 0] - T0 - 3 * (Tl - T0) / 18) < 1e-15
+    # a y- wall node away from the corners: wall links 2, 5, 6
+    assert abs(T[0, 4] - T0 - 6 * (Tb - T0) / 18) < 1e-15
+
+
+def test_corner_first_step_source():
+    """The same with lambda != rho c_V k: phi = (chi - k) lap T.  The corner
+    node's ghost neighbours: (-1, 0) open at T_l (weight 1/9), (-1, 1) open
+    at T_l (1/36), (0, -1) and (1, -1) at the wall's T_b (1/9, 1/36) and
+    (-1, -1) at the corner, which takes the y side's T_b (1/36)."""
+    lam = 0.9
+    o, rho0, T0, Tl, Tb = _corner_first_step(lam)
+    phi = o.field("phi_prev")
+    chi = lam / (rho0 * I.CV)
+    lap = 6.0 * ((1 / 9 + 1 / 36) * (Tl - T0) + (1 / 9 + 2 / 36) * (Tb - T0))
+    assert abs(phi[0, 0] - (chi - _k()) * lap) < 1e-12 * abs(lap)

@@ -79,6 +79,17 @@ SLIPS = [
      BP, "hot_spot_first_step_source"),
     ("hot spot: on the y+ wall", "  if (side == 2 && col",
      "  if (side == 3 && col", BP, "hot_spot_first_step_temperature"),
+    # corners: the wall wins, the y side gives the temperature
+    ("corner: an open side wins over a wall",
+     "    if ((ys >= 0 && h->c.bc[ys] == LBPO_BC_WALL) ||\n"
+     "        (xs >= 0 && h->c.bc[xs] == LBPO_BC_WALL))",
+     "    if ((ys >= 0 && h->c.bc[ys] == LBPO_BC_WALL) &&\n"
+     "        (xs < 0 || h->c.bc[xs] == LBPO_BC_WALL))",
+     BP, "corner_first_step_temperature"),
+    ("corner: the x side gives the temperature",
+     "    gh.T = ys >= 0 ? side_T(h, ys, x) : side_T(h, xs, x);",
+     "    gh.T = xs >= 0 ? side_T(h, xs, x) : side_T(h, ys, x);",
+     BP, "corner_first_step"),
     # buoyancy (Sec. IV.B)
     ("buoyancy: sign flipped",
      "      Fy += (h->rho[i] - h->rho_ave) * c->gy;",
