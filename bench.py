@@ -26,9 +26,11 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per lattice update: 9 f + 9 g read and written, plus the
 # phi history read and written (storage bytes / phi bytes per precision)
 BYTES_PER_LUP = {0: 36 * 8 + 2 * 8, 1: 36 * 4 + 2 * 4, 2: 36 * 4 + 2 * 4,
-                 3: 36 * 2 + 2 * 4}
+                 3: 32 * 2 + 4 * 4 + 2 * 4}
+# (FP16 deviations: the 8 moving populations of f and g in binary16, the
+# rest populations f_0, g_0 in FP32, and phi)
 PREC_NAME = {0: "FP64", 1: "FP32", 2: "FP32_SHIFTED", 3: "FP16_SHIFTED"}
-PREC_DTYPE = {0: "f64", 1: "f32", 2: "f32", 3: "f16-storage/f32"}
+PREC_DTYPE = {0: "f64", 1: "f32", 2: "f32", 3: "f16+f32-storage/f32"}
 
 
 def gpu_run(n, prec, steps, warmup, per_launch=40, model=0):
@@ -71,13 +73,17 @@ def gpu_run(n, prec, steps, warmup, per_launch=40, model=0):
         b.record(stream)
         torch.cuda.synchronize()
         dms.append(a.elapsed_time(b))
+    # the step's memory schedule without its arithmetic, same handle, tiles
+    # and state (lbpc_memory_probe)
+    probe_ms = sim.memory_probe(20) if cfg["bc"][0] == 0 else None
     d = sim.diag()
     tiles = sim.tiles()
     sim.close()
     if d["nonfinite"]:
         raise RuntimeError("non-finite state in the benchmark run")
     return ms_total / steps, kern_ms, dict(
-        cfg, tiles=tiles, diag_step_ms=sorted(dms)[len(dms) // 2])
+        cfg, tiles=tiles, diag_step_ms=sorted(dms)[len(dms) // 2],
+        probe_ms=probe_ms)
 
 
 def batch_run(count, steps, warmup, tiles=None):
@@ -125,15 +131,12 @@ def batch_run(count, steps, warmup, tiles=None):
     return ms, nodes, tune
 
 
-def ceiling_run(n, elem_bytes, tiles, reps=20, warmup=5):
-    """What the HBM delivers here, timed with HIP events on the launch stream
-    in this process (csrc/lbpc_probe.hip): (a) streaming kernels over the
-    state's f and g arrays (copy, the same with non-temporal accesses, read
-    only, write only; the best of three grid sizes each) and (b) a pull-
-    stream kernel with exactly the step's access pattern, tile shape and
-    march order and no arithmetic, which moves the step's algorithmic bytes
-    per launch.  The ceiling for the step's mixed read/write traffic is the
-    faster of the copy and the pattern kernel."""
+def ceiling_run(n, elem_bytes, reps=20, warmup=5):
+    """What the HBM delivers here to streaming kernels (csrc/lbpc_probe.hip)
+    over arrays of the state's size, the f and g of one buffer (9 n^2 values
+    each): a copy, the same with non-temporal accesses, read only and write
+    only, the best of three grid sizes each, timed with HIP events on the
+    launch stream in this process."""
     import ctypes
     import torch
     from paper_1709_04400_amd import build as B
@@ -141,17 +144,11 @@ def ceiling_run(n, elem_bytes, tiles, reps=20, warmup=5):
     vp = ctypes.c_void_p
     probe.lbpc_probe_stream.argtypes = [ctypes.c_int, vp, vp, ctypes.c_size_t,
                                         ctypes.c_int, vp]
-    probe.lbpc_probe_pattern.argtypes = [vp] * 7 + [ctypes.c_int] * 6 + [vp]
     N = n * n
     dt = torch.float64 if elem_bytes == 8 else torch.float32
     dist = [torch.ones(9 * N, dtype=dt, device="cuda") for _ in range(4)]
-    phi = [torch.ones(N, dtype=dt, device="cuda") for _ in range(2)]
-    sink = torch.empty(19 * n, dtype=dt, device="cuda")
     stream = torch.cuda.current_stream()
     sp = vp(stream.cuda_stream)
-    bw, rows = tiles["block_width"], tiles["rows"]
-    nbx = -(-n // (bw - 4))
-    W = -(-n // nbx)                        # balanced strips, as the step
     arr_bytes = 9 * N * elem_bytes
 
     def timed(fn):
@@ -166,16 +163,6 @@ def ceiling_run(n, elem_bytes, tiles, reps=20, warmup=5):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    def pattern(k):
-        a, b = (0, 2) if k % 2 == 0 else (2, 0)
-        st = probe.lbpc_probe_pattern(
-            dist[a].data_ptr(), dist[a + 1].data_ptr(), dist[b].data_ptr(),
-            dist[b + 1].data_ptr(), phi[k % 2].data_ptr(),
-            phi[1 - k % 2].data_ptr(), sink.data_ptr(), n, n, elem_bytes,
-            bw, W, rows, sp)
-        if st != 0:
-            raise RuntimeError(f"pattern probe failed ({st})")
-
     def stream_fn(kind, blocks):
         def fn(k):
             a, b = (0, 2) if k % 2 == 0 else (2, 0)
@@ -187,9 +174,6 @@ def ceiling_run(n, elem_bytes, tiles, reps=20, warmup=5):
         return fn
 
     out = {}
-    pat_ms = timed(pattern)
-    out["pattern_GBs"] = round((36 + 2) * elem_bytes * N / pat_ms / 1e6, 1)
-    out["pattern_ms"] = round(pat_ms, 5)
     for kind, name, factor in ((0, "copy", 2), (1, "copy_nontemporal", 2),
                                (2, "read_only", 1), (3, "write_only", 1)):
         best = None
@@ -200,13 +184,26 @@ def ceiling_run(n, elem_bytes, tiles, reps=20, warmup=5):
                 best = (gbs, blocks)
         out[name + "_GBs"] = round(best[0], 1)
         out[name + "_blocks"] = best[1]
-    del dist, phi, sink
+    del dist
     torch.cuda.empty_cache()
-    out["ceiling_GBs"] = max(out["pattern_GBs"], out["copy_GBs"],
-                             out["copy_nontemporal_GBs"])
-    out["pattern_tiles"] = {"block_width": bw, "strip": W, "rows": rows}
     out["bytes_each"] = 2 * arr_bytes
     return out
+
+
+def ceiling_entry(stream_ceiling, probe_ms, alg_bytes, achieved):
+    """The ceiling record of one form: the streaming probes, the step's own
+    memory schedule without arithmetic (algorithmic bytes per launch over
+    its time), and the best of the two copies as the ceiling of mixed
+    read/write traffic."""
+    c = dict(stream_ceiling)
+    if probe_ms:
+        c["step_pattern_ms"] = round(probe_ms, 5)
+        c["step_pattern_GBs"] = round(alg_bytes / (probe_ms * 1e-3) / 1e9, 1)
+    c["ceiling_GBs"] = max(c["copy_GBs"], c["copy_nontemporal_GBs"])
+    return {"ceiling": c, "ceiling_GBs": c["ceiling_GBs"],
+            "frac_of_ceiling": round(achieved / c["ceiling_GBs"], 4),
+            "frac_of_step_pattern": round(
+                achieved / c["step_pattern_GBs"], 4) if probe_ms else None}
 
 
 def _host_info():
@@ -330,7 +327,7 @@ def main():
 
     ms, kern_ms, cfg = gpu_run(args.n, 0, args.steps, args.warmup,
                                args.per_launch)
-    ceiling = ceiling_run(args.n, 8, cfg["tiles"]) if args.ceiling else None
+    ceiling = ceiling_run(args.n, 8) if args.ceiling else None
     nodes = args.n * args.n
     mlups = nodes / ms / 1e3
     alg_bytes = BYTES_PER_LUP[0] * nodes
@@ -362,10 +359,8 @@ def main():
                          alg_bytes / (ms * 1e-3) / 1e9, 1)},
     }
     if ceiling:
-        out["roofline"]["ceiling"] = ceiling
-        out["roofline"]["ceiling_GBs"] = ceiling["ceiling_GBs"]
-        out["roofline"]["frac_of_ceiling"] = round(
-            achieved / ceiling["ceiling_GBs"], 4)
+        out["roofline"].update(ceiling_entry(ceiling, cfg["probe_ms"],
+                                             alg_bytes, achieved))
     if args.variants:
         var = {}
 
@@ -386,12 +381,16 @@ def main():
                                     args.warmup)
             var[PREC_NAME[prec]] = entry(vms, vk, BYTES_PER_LUP[prec],
                                          PREC_DTYPE[prec])
+            if vcfg["probe_ms"]:
+                var[PREC_NAME[prec]]["step_pattern_ms"] = round(
+                    vcfg["probe_ms"], 5)
+                var[PREC_NAME[prec]]["frac_of_step_pattern"] = round(
+                    vcfg["probe_ms"] / vms, 4)
             if prec == 1 and args.ceiling:
-                c32 = ceiling_run(args.n, 4, vcfg["tiles"])
-                var["FP32"]["ceiling_GBs"] = c32["ceiling_GBs"]
-                var["FP32"]["frac_of_ceiling"] = round(
-                    var["FP32"]["alg_GBs"] / c32["ceiling_GBs"], 4)
-                var["FP32"]["ceiling"] = c32
+                c32 = ceiling_run(args.n, 4)
+                var["FP32"].update(ceiling_entry(
+                    c32, vcfg["probe_ms"], BYTES_PER_LUP[1] * nodes,
+                    var["FP32"]["alg_GBs"]))
         # the other thermal models on the same workload (FP64): the
         # Gong-Cheng BGK collision, which writes phi but reads no history
         # (36 x 8 + 8 B), and the BGK form of the improved model, which also

@@ -233,6 +233,17 @@ lbpc_status lbpc_get_tiles(const lbpc_handle *h, int32_t *block_width,
 lbpc_status lbpc_autotune(lbpc_handle *h, int32_t steps, int32_t *block_width,
                           int32_t *rows, double *ms_per_step);
 
+/* Measurement aid: times `launches` launches of the step kernel's memory
+ * schedule with its arithmetic left out (every node stores the values it
+ * pulls and its phi history: the same loads and stores, tile shape and
+ * march order as lbpc_step) on the current state, which it leaves as it is,
+ * and reports the mean milliseconds per launch.  The step moves the same
+ * bytes per launch, so its time over this one is the share of the bandwidth
+ * its access pattern can reach that it attains.  Periodic lattices only
+ * (LBPC_ERR_UNSUPPORTED otherwise).  Blocks until done. */
+lbpc_status lbpc_memory_probe(lbpc_handle *h, int32_t launches,
+                              double *ms_per_launch);
+
 /* Waits for the stream; writes rho, v = (j + F/2)/rho and T at the current
  * time level into host FP64 arrays [ny][nx] (any pointer may be NULL).
  * Returns LBPC_ERR_NUMERIC if a non-finite value is present. */

@@ -161,6 +161,9 @@ StepParams params_now(lbpc_handle* h) {
   p.gout = at(h, h->L.dist[1 - h->cur][1]);
   p.phi = at(h, h->L.phi);
   p.phi_out = p.phi;
+  const bool rest = rest_bytes(h->cfg) > 0;
+  p.rin = rest ? at(h, h->L.rest[h->cur]) : nullptr;
+  p.rout = rest ? at(h, h->L.rest[1 - h->cur]) : nullptr;
   p.fresh = h->fresh;
   p.phi_valid = h->phi_valid;
   p.rho_ave = h->rho_ave;
@@ -557,6 +560,41 @@ lbpc_status lbpc_autotune(lbpc_handle* h, int32_t steps, int32_t* block_width,
   if (block_width) *block_width = pick[0];
   if (rows) *rows = pick[1];
   if (ms_per_step) *ms_per_step = best / steps;
+  return LBPC_OK;
+}
+
+lbpc_status lbpc_memory_probe(lbpc_handle* h, int32_t launches,
+                              double* ms_per_launch) {
+  if (!h) return fail(nullptr, LBPC_ERR_ARG, "handle is NULL");
+  if (launches < 1 || !ms_per_launch)
+    return fail(h, LBPC_ERR_ARG, "launches < 1 or output is NULL");
+  if (!h->initialised) return fail(h, LBPC_ERR_STATE, "probe before init");
+  if (h->tiled)
+    return fail(h, LBPC_ERR_UNSUPPORTED, "memory probe: periodic lattices only");
+  // reads the current buffer and the phi history; writes the other buffer
+  // (which the next step overwrites) and phi to scratch
+  StepParams p = params_now(h);
+  p.phi_out = at(h, h->L.tune_phi);
+  hipEvent_t e0, e1;
+  HIP_TRY(h, hipEventCreate(&e0), "event");
+  hipError_t e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(h, e, "event");
+  }
+  for (int k = 0; k < 2 && e == hipSuccess; ++k)
+    e = lbpc::launch_step_probe(p, h->cfg.precision, h->stream);
+  if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+  for (int k = 0; k < launches && e == hipSuccess; ++k)
+    e = lbpc::launch_step_probe(p, h->cfg.precision, h->stream);
+  if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(h, e, "memory probe");
+  *ms_per_launch = ms / launches;
   return LBPC_OK;
 }
 

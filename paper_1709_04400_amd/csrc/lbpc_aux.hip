@@ -36,12 +36,15 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_init(StepParams p,
   m[7] = rho * (vx * vx - vy * vy);
   m[8] = rho * vx * vy;
   from_moments(m, f);
+  using C = typename Tr::C;
   S* fo = static_cast<S*>(const_cast<void*>(p.fin));
   S* go = static_cast<S*>(const_cast<void*>(p.gin));
+  float* rest = static_cast<float*>(const_cast<void*>(p.rin));
+  C d[Q];
 #pragma unroll
   for (int a = 0; a < Q; ++a)
-    Tr::st(fo, dix(p.nx, a, y, x),
-           typename Tr::C(f[a] - (Tr::shift ? w_lat(a) * p.rho_ref : 0.0)));
+    d[a] = C(f[a] - (Tr::shift ? w_lat(a) * p.rho_ref : 0.0));
+  store_node<P>(fo, rest, p.nx, y, x, d);
   if (p.gc) {
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
@@ -67,8 +70,8 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_init(StepParams p,
   }
 #pragma unroll
   for (int a = 0; a < Q; ++a)
-    Tr::st(go, dix(p.nx, a, y, x),
-           typename Tr::C(f[a] - (Tr::shift ? w_rest(p, a) * p.T_ref : 0.0)));
+    d[a] = C(f[a] - (Tr::shift ? w_rest(p, a) * p.T_ref : 0.0));
+  store_node<P>(go, rest ? rest + N : nullptr, p.nx, y, x, d);
 }
 
 // moments at the current time level: out = [rho | jx | jy | T | psi], FP64
@@ -198,6 +201,13 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_load(StepParams p, int which,
   const int a = which % Q;
   const long long y = i / p.nx;
   const long long o = dix(p.nx, a, y, (int)(i - y * p.nx));
+  if (P == 3 && a == 0) {
+    // FP16 deviation form: the rest populations are FP32 arrays
+    float* rest = static_cast<float*>(const_cast<void*>(p.rin));
+    const double sh = which < Q ? w_lat(0) * p.rho_ref : w_rest(p, 0) * p.T_ref;
+    rest[(which < Q ? 0 : N) + i] = float(in[i] - sh);
+    return;
+  }
   if (which < Q) {
     S* fo = static_cast<S*>(const_cast<void*>(p.fin));
     Tr::st(fo, o,

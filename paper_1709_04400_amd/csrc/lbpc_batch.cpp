@@ -27,6 +27,7 @@ constexpr int MIN_ROWS = 4;
 
 struct CaseLayout {
   size_t dist[2][2];
+  size_t rest[2];   // FP16 deviation form: FP32 rest populations per buffer
   size_t phi;
   size_t tune_phi;  // phi(t) written here while the autotuner times steps
 };
@@ -77,6 +78,10 @@ BatchLayout plan_batch(const lbpc_config* cfgs, int n) {
         L.cases[c].dist[b][k] = off;
         off += d;
       }
+    for (int b = 0; b < 2; ++b) {
+      L.cases[c].rest[b] = off;
+      off += align_up(rest_bytes(cfgs[c]));
+    }
     const size_t h =
         align_up(hist_arrays(cfgs[c]) * N * compute_bytes(cfgs[c].precision));
     L.cases[c].phi = off;
@@ -195,6 +200,9 @@ StepParams case_params(lbpc_batch* b, int c, int par) {
   p.gout = at(b, cl.dist[1 - par][1]);
   p.phi = at(b, cl.phi);
   p.phi_out = b->tuning ? at(b, cl.tune_phi) : p.phi;
+  const bool rest = rest_bytes(b->cfgs[c]) > 0;
+  p.rin = rest ? at(b, cl.rest[par]) : nullptr;
+  p.rout = rest ? at(b, cl.rest[1 - par]) : nullptr;
   p.fresh = b->fresh;
   p.phi_valid = b->phi_valid;
   p.rho_ave = b->rho_ave[c];

@@ -70,6 +70,9 @@ struct StepParams {
                     // followed by [N] T v_x and [N] T v_y of step t-1
   void* phi_out;    // the same for step t; the same arrays except while
                     // the autotuner times steps
+  const void* rin;  // FP16 deviation form only: the rest populations of the
+  void* rout;       // input / output buffer in FP32, [N] f_0 then [N] g_0
+                    // (deviations; direction 0 of the FP16 arrays is unused)
   long long N;      // nx * ny
   int* bad;         // set to 1 when a step meets an invalid node state
                     // (host-mapped memory, read by the host without waiting)
@@ -376,10 +379,59 @@ __device__ __forceinline__ void pull_raw(
       }
     }
   }
+  // the FP16 deviation form keeps the rest populations in FP32 arrays of
+  // their own (the image of a float in the 32-bit register)
+  constexpr int A0 = P == 3 ? 1 : 0;
+  if constexpr (P == 3) {
+    const long long o = (long long)y * nx + x;
+    const Gbl<float>* r = gbl(static_cast<const float*>(p.rin));
+    fr[0] = __float_as_uint(r[o]);
+    gr[0] = __float_as_uint(r[p.N + o]);
+  }
 #pragma unroll
-  for (int a = 0; a < Q; ++a) {
+  for (int a = A0; a < Q; ++a) {
     fr[a] = Tr::ldr(fin, off[a]);
     gr[a] = Tr::ldr(gin, off[a]);
+  }
+}
+
+// Raw register image -> compute value of direction a (the rest population
+// of the FP16 deviation form is an FP32 image).
+template <int P>
+__device__ __forceinline__ typename Prec<P>::C raw_value(
+    const typename Prec<P>::R v, int a) {
+  if constexpr (P == 3) {
+    if (a == 0) return __uint_as_float(v);
+  }
+  return Prec<P>::cvt(v);
+}
+
+// Store of the nine post-collision values d[a] (storage form: deviations
+// for the shifted forms) of one node: element dix(nx, a, y, x) of buf.  The
+// FP16 deviation form stores directions 1-8 as binary16 (round to nearest
+// even) and the rest population as FP32 in rest[y nx + x], less the rounding
+// errors of the other eight: the node's stored sum is then the computed sum
+// to FP32 rounding, so biased rounding of near-constant populations does not
+// drift the mass (or sum T) of the lattice.
+template <int P>
+__device__ __forceinline__ void store_node(typename Prec<P>::S* buf,
+                                           float* rest, int nx, long long y,
+                                           int x,
+                                           const typename Prec<P>::C d[Q]) {
+  using Tr = Prec<P>;
+  if constexpr (P == 3) {
+    float err = 0.0f;
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+      const __half h = __float2half_rn(d[a]);
+      gbl(reinterpret_cast<unsigned short*>(buf))[dix(nx, a, y, x)] =
+          __half_as_ushort(h);
+      err += __half2float(h) - d[a];
+    }
+    gbl(rest)[y * nx + x] = d[0] - err;
+  } else {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) Tr::st(buf, dix(nx, a, y, x), d[a]);
   }
 }
 
@@ -390,7 +442,7 @@ __device__ __forceinline__ void cook_f(const Shift<P>& sh,
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
     if constexpr (Prec<P>::shift)
-      f[a] = Prec<P>::cvt(fr[a]) + sh.f(a);
+      f[a] = raw_value<P>(fr[a], a) + sh.f(a);
     else
       f[a] = Prec<P>::cvt(fr[a]);
   }
@@ -405,7 +457,7 @@ __device__ __forceinline__ void cook_g(const StepParams& p, const Shift<P>& sh,
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
     if constexpr (Prec<P>::shift)
-      g[a] = Prec<P>::cvt(gr[a]) + sh.g(a);
+      g[a] = raw_value<P>(gr[a], a) + sh.g(a);
     else
       g[a] = Prec<P>::cvt(gr[a]);
   }

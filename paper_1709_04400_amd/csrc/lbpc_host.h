@@ -17,6 +17,7 @@
 namespace lbpc {
 hipError_t launch_step(const StepParams& p, int prec, hipStream_t s,
                        double* dpart = nullptr, int nostore = 0);
+hipError_t launch_step_probe(const StepParams& p, int prec, hipStream_t s);
 hipError_t launch_init(const StepParams& p, int prec, const double* in,
                        hipStream_t s);
 hipError_t launch_macro(const StepParams& p, int prec, double* io,
@@ -55,8 +56,17 @@ inline int hist_arrays(const lbpc_config& c) {
   return c.thermal_model == LBPC_THERMAL_IMPROVED_BGK ? 3 : 1;
 }
 
+// FP32 rest populations of the FP16 deviation form, per buffer: [N] f_0,
+// then [N] g_0 (none for the other forms)
+inline size_t rest_bytes(const lbpc_config& c) {
+  return c.precision == LBPC_FP16_SHIFTED
+             ? 2 * (size_t)c.nx * (size_t)c.ny * sizeof(float)
+             : 0;
+}
+
 struct Layout {
   size_t dist[2][2];  // offsets of f / g of buffer 0 / 1
+  size_t rest[2];     // FP16 deviation form: rest populations of buffer 0 / 1
   size_t phi, scratch, partial, diag_out;
   size_t table, work;  // parameter table and tile list (non-periodic path)
   size_t work_capacity;
@@ -94,6 +104,10 @@ inline Layout plan(const lbpc_config& c) {
       L.dist[b][k] = off;
       off += dbytes;
     }
+  for (int b = 0; b < 2; ++b) {
+    L.rest[b] = off;
+    off += align_up(rest_bytes(c));
+  }
   const size_t hbytes = align_up(hist_arrays(c) * N * compute_bytes(c.precision));
   L.phi = off;
   off += hbytes;

@@ -78,7 +78,10 @@ template <int P> struct StepOcc {
 // liquid area, count above the mid density, sum S0, max |v|^2, non-finite.
 constexpr int DIAG_VALS = 8;
 
-template <int P, bool GEN, int BLOCK, bool DIAG>
+// PROBE: the same loads and stores in the same schedule with the
+// arithmetic left out (each node stores the values it pulled, phi its
+// history): the memory time of the step's access pattern.
+template <int P, bool GEN, int BLOCK, bool DIAG, bool PROBE = false>
 __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
                                           int slot, double* __restrict__ dpart,
                                           bool nostore) {
@@ -226,6 +229,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
 #pragma unroll
         for (int a = 0; a < Q; ++a) s_g[k][a][t] = ga[a];
       }
+      if constexpr (!PROBE) {
       const C sa = fa[1] + fa[2] + fa[3] + fa[4];
       const C sd = fa[5] + fa[6] + fa[7] + fa[8];
       const C rho = fa[0] + sa + sd;
@@ -278,12 +282,22 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
       s_rho[sl0][t] = rho;
       s_T[sl0][t] = T;
       s_psi[sl0][t] = C(psi);
+      }  // !PROBE
     }
     __syncthreads();
 
     // ------------------------------------------------ B(r-1) and C1(r-1)
     C irn = C(0);
-    {
+    if constexpr (PROBE) {
+      const int rb = r - dir;
+      if (doC && rb >= Y0 && rb < Y1) {
+        C fo[Q];
+        cook_f<P>(sh, PD == 1 ? fq1 : F[kp], fo);
+#pragma unroll
+        for (int a = 0; a < Q; ++a) fo[a] -= sh.f(a);
+        store_node<P>(fout, static_cast<float*>(p.rout), nx, rb, c, fo);
+      }
+    } else {
       const int rb = r - dir;
       const bool ghostr = (rb < 0 || rb >= ny) && !p.pery;
       if (doB && !ghostr && rb >= Y0 - 1 && rb <= Y1) {
@@ -373,8 +387,8 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
                     (C(1) - C(0.5) * sf[k]) * Sf[k];
           from_moments(ms, fo);
 #pragma unroll
-          for (int a = 0; a < Q; ++a)
-            Tr::st(fout, dix(nx, a, rb, c), fo[a] - sh.f(a));
+          for (int a = 0; a < Q; ++a) fo[a] -= sh.f(a);
+          store_node<P>(fout, static_cast<float*>(p.rout), nx, rb, c, fo);
         }
       }
     }
@@ -411,7 +425,24 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
     __syncthreads();
 
     // -------------------------------------------------------------- C2(r-2)
-    {
+    if constexpr (PROBE) {
+      const int yc = r - 2 * dir;
+      if (doC && yc >= Y0 && yc < Y1) {
+        C go[Q];
+        if constexpr (PD == 1) {
+          cook_g<P, GEN>(p, sh, c, yc, gq2, go);
+        } else {
+#pragma unroll
+          for (int a = 0; a < Q; ++a) go[a] = s_g[k2][a][t];
+        }
+#pragma unroll
+        for (int a = 0; a < Q; ++a) go[a] -= sh.g(a);
+        phio[(long long)yc * nx + c] = hphi;
+        store_node<P>(gout,
+                      P == 3 ? static_cast<float*>(p.rout) + N : nullptr, nx,
+                      yc, c, go);
+      }
+    } else {
       const int yc = r - 2 * dir;
       const int slN = dir > 0 ? sl1 : sl3, slS = dir > 0 ? sl3 : sl1;
       if (doC && yc >= Y0 && yc < Y1) {
@@ -603,8 +634,10 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
           from_moments(ns, go);
         }
 #pragma unroll
-        for (int a = 0; a < Q; ++a)
-          Tr::st(gout, dix(nx, a, yc, c), go[a] - sh.g(a));
+        for (int a = 0; a < Q; ++a) go[a] -= sh.g(a);
+        store_node<P>(gout,
+                      P == 3 ? static_cast<float*>(p.rout) + N : nullptr, nx,
+                      yc, c, go);
         }  // !skip
       }
     }
@@ -686,6 +719,37 @@ k_step(StepParams p, double* dpart, int nostore) {
   block_tile(p, bx, by);
   step_tile<P, GEN, BLOCK, DIAG>(p, bx, by, by * p.nbx + bx, dpart,
                                  nostore != 0);
+}
+
+// The memory schedule of k_step without its arithmetic (see step_tile):
+// reads the state and the phi history, writes the other buffer and
+// phi_out (the host points phi_out at scratch).
+template <int P, int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(
+    BlockOcc<P, BLOCK>::waves, BlockOcc<P, BLOCK>::waves))) void
+k_step_probe(StepParams p) {
+  int bx, by;
+  block_tile(p, bx, by);
+  step_tile<P, false, BLOCK, false, true>(p, bx, by, 0, nullptr, false);
+}
+
+hipError_t launch_step_probe(const StepParams& p, int prec, hipStream_t s) {
+  const dim3 grid(p.nbx * p.nby);
+  if (!(p.perx && p.pery)) return hipErrorInvalidValue;
+#define LBPC_PROBE_BW(PR)                                                    \
+  if (p.bw == 512)                                                           \
+    hipLaunchKernelGGL((k_step_probe<PR, 512>), grid, dim3(512), 0, s, p);   \
+  else                                                                       \
+    hipLaunchKernelGGL((k_step_probe<PR, 256>), grid, dim3(256), 0, s, p);
+  switch (prec) {
+    case 0: LBPC_PROBE_BW(0); break;
+    case 1: LBPC_PROBE_BW(1); break;
+    case 2: LBPC_PROBE_BW(2); break;
+    case 3: LBPC_PROBE_BW(3); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef LBPC_PROBE_BW
+  return hipGetLastError();
 }
 
 // Batched form: many independent lattices, one persistent launch per step.

@@ -26,7 +26,8 @@ EXPORTS = (
     "lbpc_get_rho_u_T", "lbpc_get_diag", "lbpc_get_diag_noalloc",
     "lbpc_step_diag", "lbpc_state_bytes",
     "lbpc_save_state", "lbpc_load_state", "lbpc_destroy", "lbpc_last_error",
-    "lbpc_set_tiles", "lbpc_get_tiles", "lbpc_autotune", "lbpc_batch_workspace_bytes", "lbpc_batch_create",
+    "lbpc_set_tiles", "lbpc_get_tiles", "lbpc_autotune", "lbpc_memory_probe",
+    "lbpc_batch_workspace_bytes", "lbpc_batch_create",
     "lbpc_batch_init_fields", "lbpc_batch_set_tiles", "lbpc_batch_autotune",
     "lbpc_batch_step", "lbpc_batch_step_diag", "lbpc_batch_get_rho_u_T",
     "lbpc_batch_get_diag",
@@ -110,6 +111,7 @@ def lib():
                                      ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.lbpc_autotune.argtypes = [vp, i32, ctypes.POINTER(i32),
                                     ctypes.POINTER(i32), dp]
+        L.lbpc_memory_probe.argtypes = [vp, i32, dp]
         L.lbpc_batch_workspace_bytes.argtypes = [
             ctypes.POINTER(Config), i32, ctypes.POINTER(ctypes.c_size_t)]
         L.lbpc_batch_create.argtypes = [ctypes.POINTER(Config), i32, vp,
@@ -317,6 +319,15 @@ class Simulation:
                    self.h)
         return {"block_width": bw.value, "rows": rows.value,
                 "ms_per_step": ms.value}
+
+    def memory_probe(self, launches=20) -> float:
+        """lbpc_memory_probe: ms per launch of the step's memory schedule
+        without its arithmetic (state unchanged)."""
+        ms = ctypes.c_double()
+        with self._on():
+            _check(lib().lbpc_memory_probe(self.h, int(launches),
+                                           ctypes.byref(ms)), self.h)
+        return ms.value
 
     def diag(self) -> dict:
         with self._on():

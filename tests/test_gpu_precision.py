@@ -3,8 +3,7 @@
 FP32 (storage and arithmetic), FP32 deviations from the rest equilibrium and
 FP16 deviations with FP32 arithmetic, on the workloads' own geometries:
   * a short run against the CPU oracle;
-  * coexistence densities of a flat film (T = 0.86 Tc, 24000 steps; FP16
-    over 8000);
+  * coexistence densities of a flat film (T = 0.86 Tc, 24000 steps);
   * the droplet-radius history of the evaporation case (300 x 300, open
     fixed-T sides at 1.1 T_sat, 20000 steps, radius every 500 steps);
   * the bubble departure time on the boiling geometry (400 x 800, hot spot,
@@ -91,7 +90,6 @@ def test_coexistence_densities():
     assert abs(ref["rho_l"] - I.RHO_L) / I.RHO_L < 0.01
     assert abs(ref["rho_v"] - I.RHO_V) / I.RHO_V < 0.06
     assert abs(ref["mass_drift"]) < 1e-11
-    ref8 = _film(I.FP64, steps=8000)
     out = {"FP64": ref}
 
     def errs(r, base):
@@ -104,16 +102,17 @@ def test_coexistence_densities():
         out[NAMES[prec]] = e
         assert e["rho_l"] < 1.5e-4 and e["rho_v"] < 1e-3 and \
             e["mass_drift"] < 1e-3, (NAMES[prec], e)
-    # FP16 deviations: rounding of near-constant liquid populations is
-    # biased, so the film loses mass steadily; asserted over 8000 steps,
-    # and the 24000-step outcome is reported (it can invert the film)
-    e8 = errs(_film(I.FP16_SHIFTED, steps=8000), ref8)
+    # FP16 deviations: binary16 moving populations, FP32 rest populations
+    # that absorb the eight others' rounding errors, so biased rounding does
+    # not drain the liquid (a single FP16 reference had the film inverted by
+    # 24000 steps)
     r24 = _film(I.FP16_SHIFTED)
-    out["FP16_SHIFTED"] = {"8000_steps": e8, "24000_steps": errs(r24, ref),
-                           "film_intact_24000": r24["rho_l"] > 3.0}
-    assert e8["rho_l"] < 0.01 and e8["rho_v"] < 0.15 and \
-        e8["mass_drift"] < 0.03, e8
+    e24 = errs(r24, ref)
+    out["FP16_SHIFTED"] = dict(e24, film_intact_24000=r24["rho_l"] > 3.0)
     _report("coexistence_film", out)
+    assert r24["rho_l"] > 3.0, r24
+    assert e24["rho_l"] < 3e-3 and e24["rho_v"] < 3e-3 and \
+        e24["mass_drift"] < 3e-3, e24
 
 
 def _radius_history(prec):
@@ -134,7 +133,7 @@ def _radius_history(prec):
 def test_droplet_radius_history():
     ref = _radius_history(I.FP64)
     out = {"FP64_R0": ref[0], "FP64_R20000": ref[-1]}
-    bounds = {I.FP32: 1e-4, I.FP32_SHIFTED: 1e-4, I.FP16_SHIFTED: 0.03}
+    bounds = {I.FP32: 1e-4, I.FP32_SHIFTED: 1e-4, I.FP16_SHIFTED: 1e-3}
     for prec in REDUCED:
         h = _radius_history(prec)
         err = float(np.max(np.abs(h - ref) / ref))
@@ -154,6 +153,7 @@ def _departure(prec, max_steps=80000, every=500):
     half = 0.5 * (I.RHO_L + I.RHO_V)
     seen = False
     step = None
+    largest = 0.0     # largest attached vapour region seen (nodes)
     for k in range(max_steps // every):
         g.step(every)
         r = g.rho_u_T()[0]
@@ -169,22 +169,30 @@ def _departure(prec, max_steps=80000, every=500):
             continue
         big = int(np.argmax(sizes)) + 1
         touches = bool((lab[0] == big).any())
+        if touches:
+            largest = max(largest, float(sizes[big - 1]))
         if touches and sizes[big - 1] > 200:
             seen = True
         if seen and not touches:
             step = (k + 1) * every
             break
     g.close()
-    return step
+    return step, largest
 
 
 def test_bubble_departure_time():
-    ref = _departure(I.FP64)
+    """FP32 and FP32 deviations depart within 5 % of the FP64 step.  FP16
+    deviations: no departure within 80000 steps (FP64: 66000) when this
+    bound was set -- the binary16 quantisation of the liquid populations
+    (~7e-4 relative) changes nucleation on the hot spot -- so for that form
+    the result is stated (step, largest attached bubble), not bounded; its
+    run must stay finite (a non-finite field fails the readback)."""
+    ref, _ = _departure(I.FP64)
     assert ref is not None, "FP64 bubble did not depart"
     out = {"FP64": ref}
     for prec in (I.FP32, I.FP32_SHIFTED, I.FP16_SHIFTED):
-        s = _departure(prec)
-        out[NAMES[prec]] = {"step": s,
+        s, largest = _departure(prec)
+        out[NAMES[prec]] = {"step": s, "largest_attached": largest,
                             "rel_err": None if s is None else
                             abs(s - ref) / ref}
     _report("bubble_departure_step", out)
