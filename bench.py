@@ -52,15 +52,17 @@ def gpu_run(n, prec, steps, warmup, per_launch=40, model=0):
     torch.cuda.synchronize()
     ms_total = e0.elapsed_time(e1)
     # average duration of one step-kernel launch: an event pair around each
-    # launch, on the stream the library launches on
+    # launch, on the stream the library launches on (a launch is two steps
+    # where the form runs two per launch; reported per step)
+    spl = sim.steps_per_launch()
     evs = [(torch.cuda.Event(enable_timing=True),
             torch.cuda.Event(enable_timing=True)) for _ in range(per_launch)]
     for a, b in evs:
         a.record(stream)
-        sim.step(1)
+        sim.step(spl)
         b.record(stream)
     torch.cuda.synchronize()
-    kern_ms = sum(a.elapsed_time(b) for a, b in evs) / per_launch
+    kern_ms = sum(a.elapsed_time(b) for a, b in evs) / per_launch / spl
     # a step that also reduces the FP64 diagnostics (lbpc_step_diag: the
     # diagnostic step kernel, the final reduction and the 64-byte copy),
     # against the plain step's launch time above
@@ -83,7 +85,7 @@ def gpu_run(n, prec, steps, warmup, per_launch=40, model=0):
         raise RuntimeError("non-finite state in the benchmark run")
     return ms_total / steps, kern_ms, dict(
         cfg, tiles=tiles, diag_step_ms=sorted(dms)[len(dms) // 2],
-        probe_ms=probe_ms)
+        probe_ms=probe_ms, steps_per_launch=spl)
 
 
 def batch_run(count, steps, warmup, tiles=None):
@@ -364,23 +366,31 @@ def main():
     if args.variants:
         var = {}
 
-        def entry(vms, vk, bpl, dtype):
+        def entry(vms, vk, bpl, dtype, spl=1):
             # frac from the same timer as MLUPS (ms_per_step); the per-launch
-            # event average beside it
+            # event average (per step) beside it.  With two steps per launch
+            # the HBM moves one step's bytes for two steps: algorithmic
+            # bytes per update stay those of the method (bpl), the bytes
+            # actually moved per update are bpl / 2.
             vb = bpl * nodes / (vms * 1e-3) / 1e9
-            return {"MLUPS": round(nodes / vms / 1e3, 1),
-                    "ms_per_step": round(vms, 5), "dtype": dtype,
-                    "alg_GBs": round(vb, 1),
-                    "frac": round(vb / HBM_PEAK_GBS, 4),
-                    "kernel_avg_ms": round(vk, 5),
-                    "frac_per_launch": round(
-                        bpl * nodes / (vk * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                    "bytes_per_lup": bpl}
+            e = {"MLUPS": round(nodes / vms / 1e3, 1),
+                 "ms_per_step": round(vms, 5), "dtype": dtype,
+                 "alg_GBs": round(vb, 1),
+                 "frac": round(vb / HBM_PEAK_GBS, 4),
+                 "kernel_avg_ms": round(vk, 5),
+                 "frac_per_launch": round(
+                     bpl * nodes / (vk * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                 "bytes_per_lup": bpl, "steps_per_launch": spl}
+            if spl > 1:
+                e["hbm_bytes_per_lup"] = bpl / spl
+                e["hbm_GBs"] = round(vb / spl, 1)
+            return e
         for prec in (1, 2, 3):
             vms, vk, vcfg = gpu_run(args.n, prec, max(args.steps // 4, 50),
                                     args.warmup)
             var[PREC_NAME[prec]] = entry(vms, vk, BYTES_PER_LUP[prec],
-                                         PREC_DTYPE[prec])
+                                         PREC_DTYPE[prec],
+                                         vcfg["steps_per_launch"])
             if vcfg["probe_ms"]:
                 var[PREC_NAME[prec]]["step_pattern_ms"] = round(
                     vcfg["probe_ms"], 5)
@@ -391,6 +401,15 @@ def main():
                 var["FP32"].update(ceiling_entry(
                     c32, vcfg["probe_ms"], BYTES_PER_LUP[1] * nodes,
                     var["FP32"]["alg_GBs"]))
+        # FP32 with two steps per launch (LBPC_TWO_STEP=1, off by default)
+        os.environ["LBPC_TWO_STEP"] = "1"
+        try:
+            vms, vk, vcfg = gpu_run(args.n, 1, max(args.steps // 4, 50),
+                                    args.warmup)
+        finally:
+            os.environ.pop("LBPC_TWO_STEP")
+        var["FP32_TWO_STEP"] = entry(vms, vk, BYTES_PER_LUP[1], "f32",
+                                     vcfg["steps_per_launch"])
         # the other thermal models on the same workload (FP64): the
         # Gong-Cheng BGK collision, which writes phi but reads no history
         # (36 x 8 + 8 B), and the BGK form of the improved model, which also

@@ -47,6 +47,8 @@
  *                                  resident slot walking the list
  *   LBPC_FORCE_TILED=1, LBPC_FORCE_GEN=1   run a periodic lattice through
  *                                  the tile-list / boundary-capable kernel
+ *   LBPC_TWO_STEP=1                two time steps per launch where
+ *                                  available (lbpc_steps_per_launch)
  */
 #ifndef LBPC_H
 #define LBPC_H
@@ -225,6 +227,17 @@ lbpc_status lbpc_set_tiles(lbpc_handle *h, int32_t block_width, int32_t rows);
  * may be NULL; LBPC_ERR_ARG if h is NULL.  Host only: no device work. */
 lbpc_status lbpc_get_tiles(const lbpc_handle *h, int32_t *block_width,
                            int32_t *rows, int32_t *rows_edge);
+
+/* Time steps per launch of lbpc_step: 2 where it runs two steps in one
+ * launch (on request, LBPC_TWO_STEP=1 at creation: the FP32 and
+ * FP32-deviation forms on periodic lattices of at least 16 x 16 nodes under
+ * the improved or compromised model, without graph replay; the results
+ * agree with single steps to FP32 rounding; an odd last step runs alone),
+ * else 1.
+ * The two-step launches keep their own tile shape (256-thread blocks, one
+ * block per CU); lbpc_set_tiles and lbpc_autotune set the single-step
+ * shape.  Host only. */
+lbpc_status lbpc_steps_per_launch(const lbpc_handle *h, int32_t *steps);
 
 /* Times `steps` launches of each candidate tile shape (the shape in place;
  * block width 64, 128, 256, 512 x rows 4 ... 64 and that width's default

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbpc.so")
-SOURCES = ["lbpc_api.cpp", "lbpc_batch.cpp", "lbpc_step.hip", "lbpc_aux.hip"]
+SOURCES = ["lbpc_api.cpp", "lbpc_batch.cpp", "lbpc_step.hip", "lbpc_step2.hip",
+           "lbpc_aux.hip"]
 # memory-ceiling probes the benchmark times beside the step (own library)
 PROBE_SOURCE = "lbpc_probe.hip"
 PROBE_LIB = os.path.join(HERE, "liblbpc_probe.so")

@@ -52,6 +52,12 @@ struct lbpc_handle {
   // period (two launches), one per starting buffer
   hipGraphExec_t graph[2];
   int use_graph;
+  // two steps per launch (4-byte storage forms, periodic lattices): its own
+  // tile shape, and the phi history in one of two arrays (phi_sel), since
+  // that kernel reads phi(t-1) of nodes other blocks write phi(t+1) of
+  int two_step;
+  StepParams ts;
+  int phi_sel;
   std::string err;
 };
 
@@ -152,6 +158,12 @@ lbpc_status scratch_for_device(lbpc_handle* h, double** out) {
   return LBPC_OK;
 }
 
+// the two phi history arrays: the state's (phi_sel) and the other one,
+// scratch for launches that must not touch the history
+void* phi_buf(lbpc_handle* h, int sel) {
+  return at(h, sel ? h->L.tune_phi : h->L.phi);
+}
+
 // step parameters for the current state (input = buffer cur)
 StepParams params_now(lbpc_handle* h) {
   StepParams p = h->base;
@@ -159,7 +171,7 @@ StepParams params_now(lbpc_handle* h) {
   p.gin = at(h, h->L.dist[h->cur][1]);
   p.fout = at(h, h->L.dist[1 - h->cur][0]);
   p.gout = at(h, h->L.dist[1 - h->cur][1]);
-  p.phi = at(h, h->L.phi);
+  p.phi = phi_buf(h, h->phi_sel);
   p.phi_out = p.phi;
   const bool rest = rest_bytes(h->cfg) > 0;
   p.rin = rest ? at(h, h->L.rest[h->cur]) : nullptr;
@@ -221,7 +233,7 @@ lbpc_status prepare_step(lbpc_handle* h, bool tuning) {
     for (int par = 0; par < 2; ++par) {
       h->cur = par;
       h->table_host[par] = params_now(h);
-      if (tuning) h->table_host[par].phi_out = at(h, h->L.tune_phi);
+      if (tuning) h->table_host[par].phi_out = phi_buf(h, 1 - h->phi_sel);
     }
     h->cur = keep;
     HIP_TRY(h,
@@ -240,7 +252,7 @@ lbpc_status prepare_step(lbpc_handle* h, bool tuning) {
 // the launch alone (capturable: no uploads, no waits)
 lbpc_status launch_now(lbpc_handle* h, bool tuning) {
   StepParams p = params_now(h);
-  if (tuning) p.phi_out = at(h, h->L.tune_phi);
+  if (tuning) p.phi_out = phi_buf(h, 1 - h->phi_sel);
   if (!h->tiled)
     return lbpc::launch_step(p, h->cfg.precision, h->stream) == hipSuccess
                ? LBPC_OK
@@ -365,6 +377,19 @@ lbpc_status lbpc_create(const lbpc_config* cfg, void* dev_workspace,
     // a capturable (non-NULL) stream
     h->use_graph = h->stream != nullptr && env_int("LBPC_GRAPH", 0) != 0;
     set_tiles_impl(h, bw, rows, rows_edge);
+    h->two_step = two_step_tiles(*cfg, h->tiled != 0, h->use_graph != 0,
+                                 cus, h->ts);
+    if (h->two_step) {
+      StepParams& q = h->ts;
+      const StepParams keep = q;
+      q = h->base;  // constants of the lattice, then the two-step tiling
+      q.bw = keep.bw;
+      q.W = keep.W;
+      q.H = keep.H;
+      q.He = keep.H;
+      q.nbx = keep.nbx;
+      q.nby = keep.nby;
+    }
   }
   *out = h;
   return LBPC_OK;
@@ -388,6 +413,7 @@ lbpc_status lbpc_init_fields(lbpc_handle* h, const double* rho,
                            hipMemcpyHostToDevice, h->stream),
             "copy of the initial fields");
   h->cur = 0;
+  h->phi_sel = 0;
   StepParams p = params_now(h);
   drop_graphs(h);
   HIP_TRY(h, lbpc::launch_init(p, c.precision, scr, h->stream), "init kernel");
@@ -441,6 +467,30 @@ lbpc_status lbpc_step_diag(lbpc_handle* h, int64_t n, lbpc_diag* out) {
 namespace {
 
 lbpc_status run_steps(lbpc_handle* h, int64_t n) {
+  while (n >= 2 && h->two_step) {
+    // two steps in one launch: state buffer cur -> 1 - cur, phi history
+    // from one array to the other
+    StepParams p = params_now(h);
+    StepParams q = h->ts;
+    q.fin = p.fin;
+    q.gin = p.gin;
+    q.fout = p.fout;
+    q.gout = p.gout;
+    q.phi = p.phi;
+    q.phi_out = phi_buf(h, 1 - h->phi_sel);
+    q.fresh = p.fresh;
+    q.phi_valid = p.phi_valid;
+    q.rho_ave = p.rho_ave;
+    q.bad = p.bad;
+    HIP_TRY(h, lbpc::launch_two_steps(q, h->cfg.precision, h->stream),
+            "two-step kernel");
+    h->cur = 1 - h->cur;
+    h->phi_sel = 1 - h->phi_sel;
+    h->fresh = 0;
+    h->phi_valid = 1;
+    h->step += 2;
+    n -= 2;
+  }
   while (n > 0) {
     // steady state (state flags fixed): pairs of steps replay the graph of
     // one ping-pong period that starts from the current buffer
@@ -497,6 +547,12 @@ lbpc_status lbpc_set_tiles(lbpc_handle* h, int32_t block_width,
     return fail(h, LBPC_ERR_ARG, "block width must be 64, 128, 256 or 512");
   if (rows < 4) return fail(h, LBPC_ERR_ARG, "rows must be >= 4");
   set_tiles_impl(h, block_width, rows, rows);
+  return LBPC_OK;
+}
+
+lbpc_status lbpc_steps_per_launch(const lbpc_handle* h, int32_t* steps) {
+  if (!h || !steps) return fail(nullptr, LBPC_ERR_ARG, "NULL argument");
+  *steps = h->two_step ? 2 : 1;
   return LBPC_OK;
 }
 
@@ -574,7 +630,7 @@ lbpc_status lbpc_memory_probe(lbpc_handle* h, int32_t launches,
   // reads the current buffer and the phi history; writes the other buffer
   // (which the next step overwrites) and phi to scratch
   StepParams p = params_now(h);
-  p.phi_out = at(h, h->L.tune_phi);
+  p.phi_out = phi_buf(h, 1 - h->phi_sel);
   hipEvent_t e0, e1;
   HIP_TRY(h, hipEventCreate(&e0), "event");
   hipError_t e = hipEventCreate(&e1);
@@ -715,6 +771,7 @@ lbpc_status lbpc_load_state(lbpc_handle* h, const void* host, size_t bytes) {
   const double* src = static_cast<const double*>(host);
   drop_graphs(h);
   h->cur = 0;
+  h->phi_sel = 0;
   StepParams p = params_now(h);
   for (int which = 0; which < 18; ++which) {
     HIP_TRY(h,

@@ -18,6 +18,7 @@ namespace lbpc {
 hipError_t launch_step(const StepParams& p, int prec, hipStream_t s,
                        double* dpart = nullptr, int nostore = 0);
 hipError_t launch_step_probe(const StepParams& p, int prec, hipStream_t s);
+hipError_t launch_two_steps(const StepParams& p, int prec, hipStream_t s);
 hipError_t launch_init(const StepParams& p, int prec, const double* in,
                        hipStream_t s);
 hipError_t launch_macro(const StepParams& p, int prec, double* io,
@@ -416,6 +417,43 @@ inline void default_rows(const lbpc_config& c, bool tiled, int cus, int bw,
   strip_shape(c.nx, bw, balanced_strips(c.precision, bw), nbx, W);
   const long long slots = (long long)cus * blocks_per_cu(c.precision, bw);
   rows = rows_edge = fill_rows(c.ny, nbx, slots);
+}
+
+// Two steps per launch (lbpc_step2.hip), on request (LBPC_TWO_STEP=1): the
+// 4-byte storage forms on periodic lattices of at least 16 x 16 nodes under
+// the improved or the compromised thermal model, unless steady steps are
+// replayed from a graph.  Off by default: at 4096^2 FP32 it ran 32.1k MLUPS
+// against 34.1k for single steps (one wave per SIMD, latency-bound).  Blocks of 256 threads on strips of at most 246
+// columns (5 halo columns per side), one block per CU (134 KiB of LDS), and
+// the run height that fills whole waves of blocks, by the cost model of
+// fill_rows with 12 extra row iterations per run.  Returns whether it is
+// used; the tiling goes into q (nbx, W, nby, H, bw).
+inline bool two_step_tiles(const lbpc_config& c, bool tiled, bool graph,
+                           int cus, StepParams& q) {
+  const bool form = c.precision == LBPC_FP32 ||
+                    c.precision == LBPC_FP32_SHIFTED;
+  const bool model = c.thermal_model == LBPC_THERMAL_IMPROVED ||
+                     c.thermal_model == LBPC_THERMAL_COMPROMISED;
+  if (!form || !model || tiled || graph || c.nx < 16 || c.ny < 16 ||
+      env_int("LBPC_TWO_STEP", 0) == 0)
+    return false;
+  q.bw = 256;
+  q.nbx = (c.nx + 245) / 246;
+  q.W = (c.nx + q.nbx - 1) / q.nbx;
+  int best_rows = c.ny < 16 ? c.ny : 16;
+  long long best = -1;
+  for (int rows = best_rows; rows <= c.ny; ++rows) {
+    const long long nby = (c.ny + rows - 1) / rows;
+    const long long waves = (q.nbx * nby + cus - 1) / cus;
+    const long long cost = waves * (rows + 12);
+    if (best < 0 || cost < best) {
+      best = cost;
+      best_rows = rows;
+    }
+  }
+  q.H = best_rows;
+  q.nby = (c.ny + q.H - 1) / q.H;
+  return true;
 }
 
 // Default tile shape of a single lattice (LBPC_TILE_BW, LBPC_TILE_H and,

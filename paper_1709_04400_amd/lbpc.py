@@ -27,6 +27,7 @@ EXPORTS = (
     "lbpc_step_diag", "lbpc_state_bytes",
     "lbpc_save_state", "lbpc_load_state", "lbpc_destroy", "lbpc_last_error",
     "lbpc_set_tiles", "lbpc_get_tiles", "lbpc_autotune", "lbpc_memory_probe",
+    "lbpc_steps_per_launch",
     "lbpc_batch_workspace_bytes", "lbpc_batch_create",
     "lbpc_batch_init_fields", "lbpc_batch_set_tiles", "lbpc_batch_autotune",
     "lbpc_batch_step", "lbpc_batch_step_diag", "lbpc_batch_get_rho_u_T",
@@ -112,6 +113,7 @@ def lib():
         L.lbpc_autotune.argtypes = [vp, i32, ctypes.POINTER(i32),
                                     ctypes.POINTER(i32), dp]
         L.lbpc_memory_probe.argtypes = [vp, i32, dp]
+        L.lbpc_steps_per_launch.argtypes = [vp, ctypes.POINTER(i32)]
         L.lbpc_batch_workspace_bytes.argtypes = [
             ctypes.POINTER(Config), i32, ctypes.POINTER(ctypes.c_size_t)]
         L.lbpc_batch_create.argtypes = [ctypes.POINTER(Config), i32, vp,
@@ -309,6 +311,11 @@ class Simulation:
 
     def tiles(self) -> dict:
         return lbpc_get_tiles(self.h)
+
+    def steps_per_launch(self) -> int:
+        v = ctypes.c_int32()
+        _check(lib().lbpc_steps_per_launch(self.h, ctypes.byref(v)), self.h)
+        return v.value
 
     def autotune(self, steps=3):
         bw, rows = ctypes.c_int32(), ctypes.c_int32()
