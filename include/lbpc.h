@@ -49,6 +49,13 @@
  *                                  the tile-list / boundary-capable kernel
  *   LBPC_TWO_STEP=1                two time steps per launch where
  *                                  available (lbpc_steps_per_launch)
+ *   LBPC_STAGE_NODES=n             nodes per field of the FP64 staging
+ *                                  scratch that initial fields, readback and
+ *                                  checkpoints pass through in chunks
+ *                                  (default 2^20, never under three rows);
+ *                                  read by lbpc_workspace_bytes as well, so
+ *                                  keep it fixed between that call and
+ *                                  lbpc_create
  */
 #ifndef LBPC_H
 #define LBPC_H
@@ -176,7 +183,12 @@ typedef struct lbpc_diag {
   int32_t pad;
 } lbpc_diag;
 
-/* Device bytes the caller must provide for this configuration. */
+/* Device bytes the caller must provide for this configuration: two
+ * population buffers (each f and g, nine nx*ny arrays apiece at the storage
+ * precision, plus two FP32 rest arrays in the FP16 deviation form), two
+ * copies of the phi history, a staging scratch of at most 40 MiB by default
+ * (five FP64 fields of LBPC_STAGE_NODES nodes) and the tile list with its
+ * diagnostic records. */
 lbpc_status lbpc_workspace_bytes(const lbpc_config *cfg, size_t *bytes);
 
 /* Validates cfg and binds the workspace and stream (hipStream_t, may be

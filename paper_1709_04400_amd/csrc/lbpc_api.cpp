@@ -402,22 +402,19 @@ lbpc_status lbpc_init_fields(lbpc_handle* h, const double* rho,
   if (!rho || !ux || !uy || !T)
     return fail(h, LBPC_ERR_ARG, "field pointer is NULL");
   const lbpc_config& c = h->cfg;
-  const size_t N = (size_t)c.nx * c.ny;
   const char* bad = check_fields(c, rho, ux, uy, T, &h->rho_ave);
   if (bad) return fail(h, LBPC_ERR_ARG, bad);
   double* scr = static_cast<double*>(at(h, h->L.scratch));
   const double* src[4] = {rho, ux, uy, T};
-  for (int k = 0; k < 4; ++k)
-    HIP_TRY(h,
-            hipMemcpyAsync(scr + k * N, src[k], N * sizeof(double),
-                           hipMemcpyHostToDevice, h->stream),
-            "copy of the initial fields");
   h->cur = 0;
   h->phi_sel = 0;
   StepParams p = params_now(h);
   drop_graphs(h);
-  HIP_TRY(h, lbpc::launch_init(p, c.precision, scr, h->stream), "init kernel");
-  HIP_TRY(h, hipStreamSynchronize(h->stream), "init synchronise");
+  {
+    const char* what = "";
+    hipError_t e = stage_init(p, c.precision, scr, h->L.stage, src, h->stream, &what);
+    if (e != hipSuccess) return hip_fail(h, e, what);
+  }
   {
     lbpc_status st = reset_flag(h);
     if (st != LBPC_OK) return st;
@@ -661,17 +658,13 @@ lbpc_status lbpc_get_rho_u_T(lbpc_handle* h, double* rho, double* ux,
   const size_t N = (size_t)h->cfg.nx * h->cfg.ny;
   double* scr = static_cast<double*>(at(h, h->L.scratch));
   StepParams p = params_now(h);
-  HIP_TRY(h, lbpc::launch_macro(p, h->cfg.precision, scr, h->stream),
-          "macro kernels");
   double* dst[4] = {rho, ux, uy, T};
-  const int slot[4] = {0, 1, 2, 3};
-  for (int k = 0; k < 4; ++k)
-    if (dst[k])
-      HIP_TRY(h,
-              hipMemcpyAsync(dst[k], scr + slot[k] * N, N * sizeof(double),
-                             hipMemcpyDeviceToHost, h->stream),
-              "copy of the fields");
-  HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+  {
+    const char* what = "";
+    hipError_t e = stage_fields(p, h->cfg.precision, scr, h->L.stage, dst,
+                                  h->stream, &what);
+    if (e != hipSuccess) return hip_fail(h, e, what);
+  }
   if (flagged(h)) return fail(h, LBPC_ERR_NUMERIC, BAD_STATE);
   for (int k = 0; k < 4; ++k)
     if (dst[k])
@@ -732,26 +725,17 @@ lbpc_status lbpc_save_state(lbpc_handle* h, void* host, size_t bytes) {
   double* scr = static_cast<double*>(at(h, h->L.scratch));
   double* dst = static_cast<double*>(host);
   StepParams p = params_now(h);
-  for (int which = 0; which < 18; ++which) {
-    HIP_TRY(h, lbpc::launch_canon(p, h->cfg.precision, which, scr, h->stream),
-            "canonical-state kernel");
-    HIP_TRY(h,
-            hipMemcpyAsync(dst + which * N, scr, N * sizeof(double),
-                           hipMemcpyDeviceToHost, h->stream),
-            "state copy");
-    HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
-  }
   const int nh = hist_arrays(h->cfg);
-  for (int k = 0; k < nh; ++k) {
+  for (int which = 0; which < 18 + nh; ++which) {
     StepParams q = p;
-    q.phi = static_cast<char*>(p.phi) + k * N * compute_bytes(h->cfg.precision);
-    HIP_TRY(h, lbpc::launch_phi_out(q, h->cfg.precision, scr, h->stream),
-            "history copy kernel");
-    HIP_TRY(h,
-            hipMemcpyAsync(dst + (18 + k) * N, scr, N * sizeof(double),
-                           hipMemcpyDeviceToHost, h->stream),
-            "state copy");
-    HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+    if (which >= 18)
+      q.phi = static_cast<char*>(p.phi) +
+              (which - 18) * N * compute_bytes(h->cfg.precision);
+    const char* what = "";
+    hipError_t e = stage_state(q, h->cfg.precision, which < 18 ? which : -1,
+                               true, scr, h->L.stage, dst + which * N,
+                               h->stream, &what);
+    if (e != hipSuccess) return hip_fail(h, e, what);
   }
   int64_t meta[3];
   meta[0] = h->phi_valid;
@@ -773,26 +757,18 @@ lbpc_status lbpc_load_state(lbpc_handle* h, const void* host, size_t bytes) {
   h->cur = 0;
   h->phi_sel = 0;
   StepParams p = params_now(h);
-  for (int which = 0; which < 18; ++which) {
-    HIP_TRY(h,
-            hipMemcpyAsync(scr, src + which * N, N * sizeof(double),
-                           hipMemcpyHostToDevice, h->stream),
-            "state copy");
-    HIP_TRY(h, lbpc::launch_load(p, h->cfg.precision, which, scr, h->stream),
-            "state load kernel");
-    HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
-  }
   const int nh = hist_arrays(h->cfg);
-  for (int k = 0; k < nh; ++k) {
+  for (int which = 0; which < 18 + nh; ++which) {
     StepParams q = p;
-    q.phi = static_cast<char*>(p.phi) + k * N * compute_bytes(h->cfg.precision);
-    HIP_TRY(h,
-            hipMemcpyAsync(scr, src + (18 + k) * N, N * sizeof(double),
-                           hipMemcpyHostToDevice, h->stream),
-            "state copy");
-    HIP_TRY(h, lbpc::launch_phi_in(q, h->cfg.precision, scr, h->stream),
-            "history load kernel");
-    HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+    if (which >= 18)
+      q.phi = static_cast<char*>(p.phi) +
+              (which - 18) * N * compute_bytes(h->cfg.precision);
+    const char* what = "";
+    hipError_t e = stage_state(q, h->cfg.precision, which < 18 ? which : -1,
+                               false, scr, h->L.stage,
+                               const_cast<double*>(src + which * N),
+                               h->stream, &what);
+    if (e != hipSuccess) return hip_fail(h, e, what);
   }
   int64_t meta[3];
   std::memcpy(meta, src + (18 + nh) * N, sizeof(meta));

@@ -10,18 +10,22 @@ constexpr int AUX_BLOCK = 256;
 
 // f = M^-1 m^eq(rho, u) of the flow model, g = M^-1 m^eq(T, u) of Eq. (53)
 // (or g = g^eq(T, u) of Eq. (14) for the Gong-Cheng model, of Eq. (29) for
-// the BGK form of the improved model); the host FP64
-// fields sit in `in` as [rho | ux | uy | T], each of N values.
+// the BGK form of the improved model), for the nodes [i0, i0 + cnt); the
+// host FP64 fields of those nodes sit in `in` as [rho | ux | uy | T], each
+// of cnt values.
 template <int P>
 __global__ __launch_bounds__(AUX_BLOCK) void k_init(StepParams p,
-                                                    const double* in) {
+                                                    const double* in,
+                                                    long long i0,
+                                                    long long cnt) {
   using Tr = Prec<P>;
   using S = typename Tr::S;
   const long long N = p.N;
-  const long long i = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
-  if (i >= N) return;
-  const double rho = in[i], vx = in[N + i], vy = in[2 * N + i],
-               T = in[3 * N + i];
+  const long long li = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
+  if (li >= cnt) return;
+  const long long i = i0 + li;
+  const double rho = in[li], vx = in[cnt + li], vy = in[2 * cnt + li],
+               T = in[3 * cnt + li];
   const long long y = i / p.nx;
   const int x = (int)(i - y * p.nx);
   const double v2 = vx * vx + vy * vy;
@@ -74,16 +78,24 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_init(StepParams p,
   store_node<P>(go, rest ? rest + N : nullptr, p.nx, y, x, d);
 }
 
-// moments at the current time level: out = [rho | jx | jy | T | psi], FP64
+// Fields at the current time level, computed band by band of rows (the
+// readback needs only a band's worth of scratch): the band holds rows
+// y0 - 1 ... y0 + nr (one halo row each side, wrapped on a periodic y axis,
+// clamped otherwise), and local row j of the band is lattice row
+// y0 - 1 + j after that wrap or clamp; m = (nr + 2) nx values per field.
+
+// moments: out = [rho | jx | jy | T | psi], FP64, for the band's rows
 template <int P, bool GEN>
 __global__ __launch_bounds__(AUX_BLOCK) void k_macro1(StepParams p,
-                                                      double* out) {
+                                                      double* out, int y0,
+                                                      int nr) {
   using Tr = Prec<P>;
   using C = typename Tr::C;
-  const long long N = p.N;
-  const long long i = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
-  if (i >= N) return;
-  const int x = (int)(i % p.nx), y = (int)(i / p.nx);
+  const long long bm = (long long)(nr + 2) * p.nx;
+  const long long li = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
+  if (li >= bm) return;
+  const int x = (int)(li % p.nx);
+  const int y = wrap_or_clamp(y0 - 1 + (int)(li / p.nx), p.ny, p.pery != 0);
   C fn[Q], gn[Q];
   const Shift<P> sh(p);
   pull_node<P, GEN>(p, static_cast<const typename Tr::S*>(p.fin),
@@ -93,30 +105,39 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_macro1(StepParams p,
   to_moments(fn, m);
   const C T = gn[0] + (gn[1] + gn[2] + gn[3] + gn[4]) +
               (gn[5] + gn[6] + gn[7] + gn[8]);
-  out[i] = (double)m[0];
-  out[N + i] = (double)m[3];
-  out[2 * N + i] = (double)m[5];
-  out[3 * N + i] = (double)T;
-  out[4 * N + i] = pseudo_psi(p, (double)m[0], (double)T);
+  out[li] = (double)m[0];
+  out[bm + li] = (double)m[3];
+  out[2 * bm + li] = (double)m[5];
+  out[3 * bm + li] = (double)T;
+  out[4 * bm + li] = pseudo_psi(p, (double)m[0], (double)T);
 }
 
-// force and velocity v = (j + F/2)/rho; overwrites jx, jy with vx, vy
+// force and velocity v = (j + F/2)/rho of the band's own rows y0 ...
+// y0 + nr - 1 (local rows 1 ... nr); overwrites jx, jy with vx, vy.  A
+// neighbour's row is found in the band by its distance from the band's
+// first row (modulo ny on a periodic y axis, where a band of ny or more rows
+// repeats rows): the band holds a copy of every row it may need.
 __global__ __launch_bounds__(AUX_BLOCK) void k_macro2(StepParams p,
-                                                      double* io) {
-  const long long N = p.N;
-  const long long i = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
-  if (i >= N) return;
-  const int x = (int)(i % p.nx), y = (int)(i / p.nx);
-  const double* psi = io + 4 * N;
+                                                      double* io, int y0,
+                                                      int nr) {
+  const long long bm = (long long)(nr + 2) * p.nx;
+  const long long li = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
+  if (li >= (long long)nr * p.nx) return;
+  const int x = (int)(li % p.nx);
+  const int y = y0 + (int)(li / p.nx);
+  const long long i = li + p.nx;  // local index (row 0 is the halo)
+  const double* psi = io + 4 * bm;
   double sx = 0.0, sy = 0.0;
   const int DX[8] = {1, 0, -1, 0, 1, -1, -1, 1};
   const int DY[8] = {0, 1, 0, -1, 1, 1, -1, -1};
   for (int k = 0; k < 8; ++k) {
     Ghost gh = resolve(p, x + DX[k], y + DY[k]);
     const double w = k < 4 ? 1.0 / 3.0 : 1.0 / 12.0;
-    const long long n = (long long)gh.y * p.nx + gh.x;
+    const int j = p.pery ? ((gh.y - (y0 - 1)) % p.ny + p.ny) % p.ny
+                         : gh.y - (y0 - 1);
+    const long long n = (long long)j * p.nx + gh.x;
     const double pn = p.wet && gh.kind == GH_WALL
-                          ? wall_psi(p, io[n], io[3 * N + n])
+                          ? wall_psi(p, io[n], io[3 * bm + n])
                           : psi[n];
     sx += w * pn * DX[k];
     sy += w * pn * DY[k];
@@ -124,8 +145,8 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_macro2(StepParams p,
   const double rho = io[i];
   double Fx = -p.G * psi[i] * sx + (rho - p.rho_ave) * p.gx;
   double Fy = -p.G * psi[i] * sy + (rho - p.rho_ave) * p.gy;
-  io[N + i] = (io[N + i] + 0.5 * Fx) / rho;
-  io[2 * N + i] = (io[2 * N + i] + 0.5 * Fy) / rho;
+  io[bm + i] = (io[bm + i] + 0.5 * Fx) / rho;
+  io[2 * bm + i] = (io[2 * bm + i] + 0.5 * Fy) / rho;
 }
 
 // Final pass of the diagnostics: block c reduces the tile records
@@ -165,15 +186,17 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_diag_reduce(
   if (t < 8) out[(long long)c * 8 + t] = red[t][0];
 }
 
-// canonical FP64 f(t) (which = 0..8) or g(t) (which = 9..17), one direction
+// canonical FP64 f(t) (which = 0..8) or g(t) (which = 9..17), one direction,
+// for the nodes [i0, i0 + cnt) into out[0 .. cnt)
 template <int P, bool GEN>
 __global__ __launch_bounds__(AUX_BLOCK) void k_canon(StepParams p, int which,
-                                                     double* out) {
+                                                     double* out, long long i0,
+                                                     long long cnt) {
   using Tr = Prec<P>;
   using C = typename Tr::C;
-  const long long N = p.N;
-  const long long i = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
-  if (i >= N) return;
+  const long long li = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
+  if (li >= cnt) return;
+  const long long i = i0 + li;
   const int x = (int)(i % p.nx), y = (int)(i / p.nx);
   C fn[Q], gn[Q];
   const Shift<P> sh(p);
@@ -186,18 +209,22 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_canon(StepParams p, int which,
     if (which == a) v = fn[a];
     if (which == Q + a) v = gn[a];
   }
-  out[i] = (double)v;
+  out[li] = (double)v;
 }
 
-// FP64 canonical direction `which` -> storage buffer (fresh layout)
+// FP64 canonical direction `which` of the nodes [i0, i0 + cnt), held in
+// in[0 .. cnt) -> storage buffer (fresh layout)
 template <int P>
 __global__ __launch_bounds__(AUX_BLOCK) void k_load(StepParams p, int which,
-                                                    const double* in) {
+                                                    const double* in,
+                                                    long long i0,
+                                                    long long cnt) {
   using Tr = Prec<P>;
   using S = typename Tr::S;
   const long long N = p.N;
-  const long long i = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
-  if (i >= N) return;
+  const long long li = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
+  if (li >= cnt) return;
+  const long long i = i0 + li;  // node; its value is in[li]
   const int a = which % Q;
   const long long y = i / p.nx;
   const long long o = dix(p.nx, a, y, (int)(i - y * p.nx));
@@ -205,33 +232,36 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_load(StepParams p, int which,
     // FP16 deviation form: the rest populations are FP32 arrays
     float* rest = static_cast<float*>(const_cast<void*>(p.rin));
     const double sh = which < Q ? w_lat(0) * p.rho_ref : w_rest(p, 0) * p.T_ref;
-    rest[(which < Q ? 0 : N) + i] = float(in[i] - sh);
+    rest[(which < Q ? 0 : N) + i] = float(in[li] - sh);
     return;
   }
   if (which < Q) {
     S* fo = static_cast<S*>(const_cast<void*>(p.fin));
     Tr::st(fo, o,
-           typename Tr::C(in[i] - (Tr::shift ? w_lat(a) * p.rho_ref : 0.0)));
+           typename Tr::C(in[li] - (Tr::shift ? w_lat(a) * p.rho_ref : 0.0)));
   } else {
     S* go = static_cast<S*>(const_cast<void*>(p.gin));
     Tr::st(go, o,
-           typename Tr::C(in[i] - (Tr::shift ? w_rest(p, a) * p.T_ref : 0.0)));
+           typename Tr::C(in[li] - (Tr::shift ? w_rest(p, a) * p.T_ref : 0.0)));
   }
 }
 
 // phi history between its compute precision and FP64
+// (nodes [i0, i0 + cnt); `out` / `in` hold that chunk)
 template <class C>
-__global__ __launch_bounds__(AUX_BLOCK) void k_phi_out(long long N,
+__global__ __launch_bounds__(AUX_BLOCK) void k_phi_out(long long i0,
+                                                       long long cnt,
                                                        const C* phi,
                                                        double* out) {
-  const long long i = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
-  if (i < N) out[i] = (double)phi[i];
+  const long long li = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
+  if (li < cnt) out[li] = (double)phi[i0 + li];
 }
 template <class C>
-__global__ __launch_bounds__(AUX_BLOCK) void k_phi_in(long long N, C* phi,
+__global__ __launch_bounds__(AUX_BLOCK) void k_phi_in(long long i0,
+                                                      long long cnt, C* phi,
                                                       const double* in) {
-  const long long i = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
-  if (i < N) phi[i] = C(in[i]);
+  const long long li = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
+  if (li < cnt) phi[i0 + li] = C(in[li]);
 }
 
 // ------------------------------------------------------------- launchers
@@ -250,27 +280,28 @@ static inline unsigned nblocks(long long N) {
   }
 
 hipError_t launch_init(const StepParams& p, int prec, const double* in,
-                       hipStream_t s) {
-#define X(PR) hipLaunchKernelGGL(k_init<PR>, dim3(nblocks(p.N)), dim3(AUX_BLOCK), 0, s, p, in)
+                       long long i0, long long cnt, hipStream_t s) {
+#define X(PR) hipLaunchKernelGGL(k_init<PR>, dim3(nblocks(cnt)), dim3(AUX_BLOCK), 0, s, p, in, i0, cnt)
   LBPC_PREC_SWITCH(prec, X)
 #undef X
   return hipGetLastError();
 }
 
-hipError_t launch_macro(const StepParams& p, int prec, double* io,
-                        hipStream_t s) {
+hipError_t launch_macro(const StepParams& p, int prec, double* io, int y0,
+                        int nr, hipStream_t s) {
   const bool gen = !(p.perx && p.pery);
+  const long long m = (long long)(nr + 2) * p.nx;
 #define X(PR)                                                                    \
   if (gen)                                                                       \
-    hipLaunchKernelGGL((k_macro1<PR, true>), dim3(nblocks(p.N)), dim3(AUX_BLOCK), 0, s, p, io); \
+    hipLaunchKernelGGL((k_macro1<PR, true>), dim3(nblocks(m)), dim3(AUX_BLOCK), 0, s, p, io, y0, nr); \
   else                                                                           \
-    hipLaunchKernelGGL((k_macro1<PR, false>), dim3(nblocks(p.N)), dim3(AUX_BLOCK), 0, s, p, io);
+    hipLaunchKernelGGL((k_macro1<PR, false>), dim3(nblocks(m)), dim3(AUX_BLOCK), 0, s, p, io, y0, nr);
   LBPC_PREC_SWITCH(prec, X)
 #undef X
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_macro2, dim3(nblocks(p.N)), dim3(AUX_BLOCK), 0, s, p,
-                     io);
+  hipLaunchKernelGGL(k_macro2, dim3(nblocks((long long)nr * p.nx)),
+                     dim3(AUX_BLOCK), 0, s, p, io, y0, nr);
   return hipGetLastError();
 }
 
@@ -282,45 +313,46 @@ hipError_t launch_diag_reduce(const double* part, const int* ranges, int lo,
 }
 
 hipError_t launch_canon(const StepParams& p, int prec, int which, double* out,
-                        hipStream_t s) {
+                        long long i0, long long cnt, hipStream_t s) {
   const bool gen = !(p.perx && p.pery);
 #define X(PR)                                                                    \
   if (gen)                                                                       \
-    hipLaunchKernelGGL((k_canon<PR, true>), dim3(nblocks(p.N)), dim3(AUX_BLOCK), 0, s, p, which, out); \
+    hipLaunchKernelGGL((k_canon<PR, true>), dim3(nblocks(cnt)), dim3(AUX_BLOCK), 0, s, p, which, out, i0, cnt); \
   else                                                                           \
-    hipLaunchKernelGGL((k_canon<PR, false>), dim3(nblocks(p.N)), dim3(AUX_BLOCK), 0, s, p, which, out);
+    hipLaunchKernelGGL((k_canon<PR, false>), dim3(nblocks(cnt)), dim3(AUX_BLOCK), 0, s, p, which, out, i0, cnt);
   LBPC_PREC_SWITCH(prec, X)
 #undef X
   return hipGetLastError();
 }
 
 hipError_t launch_load(const StepParams& p, int prec, int which,
-                       const double* in, hipStream_t s) {
-#define X(PR) hipLaunchKernelGGL(k_load<PR>, dim3(nblocks(p.N)), dim3(AUX_BLOCK), 0, s, p, which, in)
+                       const double* in, long long i0, long long cnt,
+                       hipStream_t s) {
+#define X(PR) hipLaunchKernelGGL(k_load<PR>, dim3(nblocks(cnt)), dim3(AUX_BLOCK), 0, s, p, which, in, i0, cnt)
   LBPC_PREC_SWITCH(prec, X)
 #undef X
   return hipGetLastError();
 }
 
 hipError_t launch_phi_out(const StepParams& p, int prec, double* out,
-                          hipStream_t s) {
+                          long long i0, long long cnt, hipStream_t s) {
   if (prec == 0)
-    hipLaunchKernelGGL(k_phi_out<double>, dim3(nblocks(p.N)), dim3(AUX_BLOCK),
-                       0, s, p.N, static_cast<const double*>(p.phi), out);
+    hipLaunchKernelGGL(k_phi_out<double>, dim3(nblocks(cnt)), dim3(AUX_BLOCK),
+                       0, s, i0, cnt, static_cast<const double*>(p.phi), out);
   else
-    hipLaunchKernelGGL(k_phi_out<float>, dim3(nblocks(p.N)), dim3(AUX_BLOCK),
-                       0, s, p.N, static_cast<const float*>(p.phi), out);
+    hipLaunchKernelGGL(k_phi_out<float>, dim3(nblocks(cnt)), dim3(AUX_BLOCK),
+                       0, s, i0, cnt, static_cast<const float*>(p.phi), out);
   return hipGetLastError();
 }
 
 hipError_t launch_phi_in(const StepParams& p, int prec, const double* in,
-                         hipStream_t s) {
+                         long long i0, long long cnt, hipStream_t s) {
   if (prec == 0)
-    hipLaunchKernelGGL(k_phi_in<double>, dim3(nblocks(p.N)), dim3(AUX_BLOCK),
-                       0, s, p.N, static_cast<double*>(p.phi), in);
+    hipLaunchKernelGGL(k_phi_in<double>, dim3(nblocks(cnt)), dim3(AUX_BLOCK),
+                       0, s, i0, cnt, static_cast<double*>(p.phi), in);
   else
-    hipLaunchKernelGGL(k_phi_in<float>, dim3(nblocks(p.N)), dim3(AUX_BLOCK),
-                       0, s, p.N, static_cast<float*>(p.phi), in);
+    hipLaunchKernelGGL(k_phi_in<float>, dim3(nblocks(cnt)), dim3(AUX_BLOCK),
+                       0, s, i0, cnt, static_cast<float*>(p.phi), in);
   return hipGetLastError();
 }
 

@@ -36,6 +36,7 @@ struct BatchLayout {
   // partial: one diagnostic record (8 FP64) per work item; ranges: the
   // records of each lattice; diag_out: 8 FP64 results per lattice
   size_t table, work, scratch, partial, ranges, diag_out;
+  size_t stage;          // nodes per field of the staging scratch
   size_t work_capacity;  // items
   std::vector<CaseLayout> cases;
   size_t total;
@@ -58,11 +59,12 @@ BatchLayout plan_batch(const lbpc_config* cfgs, int n) {
   L.work_capacity = max_items(cfgs, n, MIN_ROWS);
   L.work = off;
   off += align_up(L.work_capacity * sizeof(WorkItem));
-  size_t maxN = 0;
+  const size_t cap = stage_cap();
+  L.stage = 0;
   for (int c = 0; c < n; ++c)
-    maxN = std::max(maxN, (size_t)cfgs[c].nx * (size_t)cfgs[c].ny);
+    L.stage = std::max(L.stage, stage_nodes(cfgs[c].nx, cfgs[c].ny, cap));
   L.scratch = off;
-  off += align_up(5 * maxN * sizeof(double));
+  off += align_up(5 * L.stage * sizeof(double));
   L.partial = off;
   off += align_up(L.work_capacity * 8 * sizeof(double));
   L.ranges = off;
@@ -415,17 +417,13 @@ lbpc_status lbpc_batch_init_fields(lbpc_batch* b, int32_t c,
     lbpc_status st = ensure_flags(b);
     if (st != LBPC_OK) return st;
   }
-  const size_t N = (size_t)b->cfgs[c].nx * b->cfgs[c].ny;
   double* scr = static_cast<double*>(at(b, b->L.scratch));
   const double* src[4] = {rho, ux, uy, T};
-  for (int k = 0; k < 4; ++k)
-    BHIP(b,
-         hipMemcpyAsync(scr + k * N, src[k], N * sizeof(double),
-                        hipMemcpyHostToDevice, b->stream),
-         "copy of the initial fields");
   StepParams p = case_params(b, c, b->cur);
-  BHIP(b, lbpc::launch_init(p, b->prec, scr, b->stream), "init kernel");
-  BHIP(b, hipStreamSynchronize(b->stream), "synchronise");
+  {
+    const char* what = "";
+    BHIP(b, stage_init(p, b->prec, scr, b->L.stage, src, b->stream, &what), what);
+  }
   b->bad_host[c] = 0;
   b->initialised[c] = 1;
   b->fresh = 1;
@@ -602,15 +600,11 @@ lbpc_status lbpc_batch_get_rho_u_T(lbpc_batch* b, int32_t c, double* rho,
   const size_t N = (size_t)b->cfgs[c].nx * b->cfgs[c].ny;
   double* scr = static_cast<double*>(at(b, b->L.scratch));
   StepParams p = case_params(b, c, b->cur);
-  BHIP(b, lbpc::launch_macro(p, b->prec, scr, b->stream), "macro kernels");
   double* dst[4] = {rho, ux, uy, T};
-  for (int k = 0; k < 4; ++k)
-    if (dst[k])
-      BHIP(b,
-           hipMemcpyAsync(dst[k], scr + k * N, N * sizeof(double),
-                          hipMemcpyDeviceToHost, b->stream),
-           "copy of the fields");
-  BHIP(b, hipStreamSynchronize(b->stream), "synchronise");
+  {
+    const char* what = "";
+    BHIP(b, stage_fields(p, b->prec, scr, b->L.stage, dst, b->stream, &what), what);
+  }
   if (flagged(b, c)) return bfail(b, LBPC_ERR_NUMERIC, BAD_STATE);
   for (int k = 0; k < 4; ++k)
     if (dst[k])

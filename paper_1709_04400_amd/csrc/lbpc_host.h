@@ -4,6 +4,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstdlib>
@@ -20,19 +21,20 @@ hipError_t launch_step(const StepParams& p, int prec, hipStream_t s,
 hipError_t launch_step_probe(const StepParams& p, int prec, hipStream_t s);
 hipError_t launch_two_steps(const StepParams& p, int prec, hipStream_t s);
 hipError_t launch_init(const StepParams& p, int prec, const double* in,
-                       hipStream_t s);
-hipError_t launch_macro(const StepParams& p, int prec, double* io,
-                        hipStream_t s);
+                       long long i0, long long cnt, hipStream_t s);
+hipError_t launch_macro(const StepParams& p, int prec, double* io, int y0,
+                        int nr, hipStream_t s);
 hipError_t launch_diag_reduce(const double* part, const int* ranges, int lo,
                               int hi, int nlat, double* out, hipStream_t s);
 hipError_t launch_canon(const StepParams& p, int prec, int which, double* out,
-                        hipStream_t s);
+                        long long i0, long long cnt, hipStream_t s);
 hipError_t launch_load(const StepParams& p, int prec, int which,
-                       const double* in, hipStream_t s);
+                       const double* in, long long i0, long long cnt,
+                       hipStream_t s);
 hipError_t launch_phi_out(const StepParams& p, int prec, double* out,
-                          hipStream_t s);
+                          long long i0, long long cnt, hipStream_t s);
 hipError_t launch_phi_in(const StepParams& p, int prec, const double* in,
-                         hipStream_t s);
+                         long long i0, long long cnt, hipStream_t s);
 hipError_t launch_step_batch(const StepParams* table, const void* work,
                              int nwork, int parity, int grid, int prec,
                              int bw, hipStream_t s, bool gen = true,
@@ -65,10 +67,28 @@ inline size_t rest_bytes(const lbpc_config& c) {
              : 0;
 }
 
+// Nodes per field of the FP64 staging scratch through which initial
+// fields, field readback and checkpoints pass, in chunks of nodes or bands
+// of rows: the whole lattice and its two halo rows when that is at most
+// `cap` nodes, else `cap` nodes (never under three rows, the smallest
+// band).  Five fields of it: with the default cap of 2^20 nodes, 40 MiB
+// instead of 40 B per node.  LBPC_STAGE_NODES sets the cap when a handle is
+// created (smaller caps exercise the chunked transfers on small lattices).
+inline size_t stage_cap() {
+  const char* v = std::getenv("LBPC_STAGE_NODES");
+  const long long c = v ? std::atoll(v) : 0;
+  return c > 0 ? (size_t)c : (size_t)1 << 20;
+}
+inline size_t stage_nodes(int nx, int ny, size_t cap) {
+  const size_t whole = ((size_t)ny + 2) * (size_t)nx;
+  return std::min(whole, std::max(cap, 3 * (size_t)nx));
+}
+
 struct Layout {
   size_t dist[2][2];  // offsets of f / g of buffer 0 / 1
   size_t rest[2];     // FP16 deviation form: rest populations of buffer 0 / 1
   size_t phi, scratch, partial, diag_out;
+  size_t stage;        // nodes per field of the staging scratch
   size_t table, work;  // parameter table and tile list (non-periodic path)
   size_t work_capacity;
   size_t tune_phi;     // phi(t) of the autotuner's timing launches
@@ -112,8 +132,9 @@ inline Layout plan(const lbpc_config& c) {
   const size_t hbytes = align_up(hist_arrays(c) * N * compute_bytes(c.precision));
   L.phi = off;
   off += hbytes;
+  L.stage = stage_nodes(c.nx, c.ny, stage_cap());
   L.scratch = off;
-  off += align_up(5 * N * sizeof(double));
+  off += align_up(5 * L.stage * sizeof(double));
   // tiles of the narrowest strips (60 columns) and shortest runs (4 rows):
   // the most any tile shape makes, each with one diagnostic record
   L.work_capacity = (size_t)((c.nx + 59) / 60) * (size_t)((c.ny + 3) / 4);
@@ -479,6 +500,92 @@ inline void default_tiles(const lbpc_config& c, bool tiled, int cus, int& bw,
   } else {
     default_rows(c, tiled, cus, bw, rows, rows_edge);
   }
+}
+
+// Transfers through the staging scratch `scr` (five fields of `stage` FP64
+// values, stage >= 3 nx), chunk by chunk on stream s.  Stream order
+// keeps each chunk's kernel ahead of the copy that refills the scratch.
+// Each returns the first HIP error, with the failing call named in *what,
+// after synchronising s.
+
+// Initial fields (host rho, ux, uy, T of N nodes each) -> populations.
+inline hipError_t stage_init(const StepParams& p, int prec, double* scr,
+                             size_t stage, const double* const src[4],
+                             hipStream_t s, const char** what) {
+  const long long N = p.N;
+  const long long C = (long long)stage * 5 / 4;
+  hipError_t e = hipSuccess;
+  for (long long i0 = 0; i0 < N && e == hipSuccess; i0 += C) {
+    const long long cnt = std::min(C, N - i0);
+    *what = "copy of the initial fields";
+    for (int k = 0; k < 4 && e == hipSuccess; ++k)
+      e = hipMemcpyAsync(scr + k * cnt, src[k] + i0, cnt * sizeof(double),
+                         hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) break;
+    *what = "init kernel";
+    e = lbpc::launch_init(p, prec, scr, i0, cnt, s);
+  }
+  if (e != hipSuccess) return e;
+  *what = "synchronise";
+  return hipStreamSynchronize(s);
+}
+
+// Fields rho, ux, uy, T at the current time level -> host arrays of N
+// nodes (a NULL destination is skipped), band by band of rows.
+inline hipError_t stage_fields(const StepParams& p, int prec, double* scr,
+                               size_t stage, double* const dst[4],
+                               hipStream_t s, const char** what) {
+  const int R = (int)std::min(stage / (size_t)p.nx - 2, (size_t)p.ny);
+  hipError_t e = hipSuccess;
+  for (int y0 = 0; y0 < p.ny && e == hipSuccess; y0 += R) {
+    const int nr = std::min(R, p.ny - y0);
+    const size_t m = (size_t)(nr + 2) * p.nx;
+    *what = "macro kernels";
+    e = lbpc::launch_macro(p, prec, scr, y0, nr, s);
+    *what = "copy of the fields";
+    for (int k = 0; k < 4 && e == hipSuccess; ++k)
+      if (dst[k])
+        e = hipMemcpyAsync(dst[k] + (size_t)y0 * p.nx, scr + k * m + p.nx,
+                           (size_t)nr * p.nx * sizeof(double),
+                           hipMemcpyDeviceToHost, s);
+  }
+  if (e != hipSuccess) return e;
+  *what = "synchronise";
+  return hipStreamSynchronize(s);
+}
+
+// One FP64 array of N nodes of the checkpoint, device -> host (out) or
+// host -> device (!out): which 0-8 / 9-17 the canonical f / g populations,
+// which < 0 the history array at p.phi.
+inline hipError_t stage_state(const StepParams& p, int prec, int which,
+                              bool out, double* scr, size_t stage,
+                              double* host, hipStream_t s, const char** what) {
+  const long long N = p.N;
+  const long long C = (long long)stage * 5;
+  hipError_t e = hipSuccess;
+  for (long long i0 = 0; i0 < N && e == hipSuccess; i0 += C) {
+    const long long cnt = std::min(C, N - i0);
+    if (out) {
+      *what = which < 0 ? "history copy kernel" : "canonical-state kernel";
+      e = which < 0 ? lbpc::launch_phi_out(p, prec, scr, i0, cnt, s)
+                    : lbpc::launch_canon(p, prec, which, scr, i0, cnt, s);
+      if (e != hipSuccess) break;
+      *what = "state copy";
+      e = hipMemcpyAsync(host + i0, scr, cnt * sizeof(double),
+                         hipMemcpyDeviceToHost, s);
+    } else {
+      *what = "state copy";
+      e = hipMemcpyAsync(scr, host + i0, cnt * sizeof(double),
+                         hipMemcpyHostToDevice, s);
+      if (e != hipSuccess) break;
+      *what = which < 0 ? "history load kernel" : "state load kernel";
+      e = which < 0 ? lbpc::launch_phi_in(p, prec, scr, i0, cnt, s)
+                    : lbpc::launch_load(p, prec, which, scr, i0, cnt, s);
+    }
+  }
+  if (e != hipSuccess) return e;
+  *what = "synchronise";
+  return hipStreamSynchronize(s);
 }
 
 }  // namespace lbpc_host
