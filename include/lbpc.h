@@ -85,7 +85,10 @@ typedef enum {
  * pressure and p - rho c_s^2, and the diagnostic sums are always FP64).  The
  * shifted forms store f_a - w_a rho_ref and g_a - wg_a T_ref, with w the
  * D2Q9 weights and wg = (5/9, 1/18, ..., 1/18) the rest equilibrium of
- * Eq. (53). */
+ * Eq. (53).  LBPC_FP16_SHIFTED keeps the deviations of directions 1-8 as
+ * binary16, f and g of a direction in one 32-bit word, and the rest
+ * populations as an FP32 pair per node, each less the rounding errors of
+ * its node's other eight. */
 typedef enum {
   LBPC_FP64 = 0,
   LBPC_FP32 = 1,
@@ -184,8 +187,9 @@ typedef struct lbpc_diag {
 } lbpc_diag;
 
 /* Device bytes the caller must provide for this configuration: two
- * population buffers (each f and g, nine nx*ny arrays apiece at the storage
- * precision, plus two FP32 rest arrays in the FP16 deviation form), two
+ * population buffers (f and g, nine nx*ny arrays apiece at the storage
+ * precision; in the FP16 deviation form nine arrays of (f, g) words and an
+ * FP32 rest pair per node), two
  * copies of the phi history, a staging scratch of at most 40 MiB by default
  * (five FP64 fields of LBPC_STAGE_NODES nodes) and the tile list with its
  * diagnostic records. */

@@ -20,7 +20,6 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_init(StepParams p,
                                                     long long cnt) {
   using Tr = Prec<P>;
   using S = typename Tr::S;
-  const long long N = p.N;
   const long long li = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
   if (li >= cnt) return;
   const long long i = i0 + li;
@@ -43,12 +42,17 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_init(StepParams p,
   using C = typename Tr::C;
   S* fo = static_cast<S*>(const_cast<void*>(p.fin));
   S* go = static_cast<S*>(const_cast<void*>(p.gin));
-  float* rest = static_cast<float*>(const_cast<void*>(p.rin));
   C d[Q];
 #pragma unroll
   for (int a = 0; a < Q; ++a)
     d[a] = C(f[a] - (Tr::shift ? w_lat(a) * p.rho_ref : 0.0));
-  store_node<P>(fo, rest, p.nx, y, x, d);
+  // FP16 deviation form: f waits as binary16 bits for the (f, g) pairs
+  unsigned int hf[Q];
+  float rf = 0.0f;
+  if constexpr (P == 3)
+    half_node(d, hf, rf);
+  else
+    store_node<P>(fo, p.nx, y, x, d);
   if (p.gc) {
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
@@ -75,7 +79,14 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_init(StepParams p,
 #pragma unroll
   for (int a = 0; a < Q; ++a)
     d[a] = C(f[a] - (Tr::shift ? w_rest(p, a) * p.T_ref : 0.0));
-  store_node<P>(go, rest ? rest + N : nullptr, p.nx, y, x, d);
+  if constexpr (P == 3) {
+    unsigned int hg[Q];
+    float rg;
+    half_node(d, hg, rg);
+    store_pairs(fo, const_cast<void*>(p.rin), p.nx, y, x, hf, rf, hg, rg);
+  } else {
+    store_node<P>(go, p.nx, y, x, d);
+  }
 }
 
 // Fields at the current time level, computed band by band of rows (the
@@ -221,21 +232,28 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_load(StepParams p, int which,
                                                     long long cnt) {
   using Tr = Prec<P>;
   using S = typename Tr::S;
-  const long long N = p.N;
   const long long li = (long long)blockIdx.x * AUX_BLOCK + threadIdx.x;
   if (li >= cnt) return;
   const long long i = i0 + li;  // node; its value is in[li]
   const int a = which % Q;
   const long long y = i / p.nx;
   const long long o = dix(p.nx, a, y, (int)(i - y * p.nx));
-  if (P == 3 && a == 0) {
-    // FP16 deviation form: the rest populations are FP32 arrays
-    float* rest = static_cast<float*>(const_cast<void*>(p.rin));
-    const double sh = which < Q ? w_lat(0) * p.rho_ref : w_rest(p, 0) * p.T_ref;
-    rest[(which < Q ? 0 : N) + i] = float(in[li] - sh);
+  if constexpr (P == 3) {
+    // FP16 deviation form: f is the low half (the first of the pair in
+    // memory), g the high half, of the (f, g) word of direction a, and the
+    // rest populations an FP32 (f_0, g_0) pair per node
+    const int half = which < Q ? 0 : 1;
+    const double sh = which < Q ? w_lat(a) * p.rho_ref : w_rest(p, a) * p.T_ref;
+    if (a == 0) {
+      float* rest = static_cast<float*>(const_cast<void*>(p.rin));
+      rest[2 * i + half] = float(in[li] - sh);
+    } else {
+      unsigned short* h =
+          static_cast<unsigned short*>(const_cast<void*>(p.fin));
+      h[2 * o + half] = __half_as_ushort(__float2half_rn(float(in[li] - sh)));
+    }
     return;
-  }
-  if (which < Q) {
+  } else if (which < Q) {
     S* fo = static_cast<S*>(const_cast<void*>(p.fin));
     Tr::st(fo, o,
            typename Tr::C(in[li] - (Tr::shift ? w_lat(a) * p.rho_ref : 0.0)));

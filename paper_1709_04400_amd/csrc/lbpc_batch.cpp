@@ -74,12 +74,14 @@ BatchLayout plan_batch(const lbpc_config* cfgs, int n) {
   L.cases.resize(n);
   for (int c = 0; c < n; ++c) {
     const size_t N = (size_t)cfgs[c].nx * cfgs[c].ny;
-    const size_t d = align_up(9 * N * store_bytes(cfgs[c].precision));
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 2; ++b) {
       for (int k = 0; k < 2; ++k) {
         L.cases[c].dist[b][k] = off;
-        off += d;
+        off += align_up(dist_bytes(cfgs[c], k));
       }
+      if (dist_bytes(cfgs[c], 1) == 0)
+        L.cases[c].dist[b][1] = L.cases[c].dist[b][0];
+    }
     for (int b = 0; b < 2; ++b) {
       L.cases[c].rest[b] = off;
       off += align_up(rest_bytes(cfgs[c]));

@@ -126,23 +126,21 @@ template <> struct Prec<2> {  // FP32 deviations from the rest equilibrium
   __device__ static C ld(const S* p, long long i) { return gbl(p)[i]; }
   __device__ static void st(S* p, long long i, C v) { gbl(p)[i] = v; }
 };
-template <> struct Prec<3> {  // FP16 deviations, FP32 arithmetic
-  using S = __half;
+// FP16 deviations, FP32 arithmetic.  f and g of one direction share a
+// 32-bit word (binary16 f in the low half, g in the high half): they stream
+// from the same node, so one 4-byte access per lane moves both, where
+// separate arrays would take two 2-byte accesses.
+template <> struct Prec<3> {
+  using S = unsigned int;  // the (f, g) word
   using C = float;
-  // the binary16 bits, one value per 32-bit register (packing two would
-  // need the loads to have landed)
-  using R = unsigned int;
+  using R = unsigned int;  // the word as loaded
   static constexpr bool shift = true;
-  __device__ static R ldr(const S* p, long long i) {
-    return gbl(reinterpret_cast<const unsigned short*>(p))[i];
-  }
-  __device__ static C cvt(R v) {
+  __device__ static R ldr(const S* p, long long i) { return gbl(p)[i]; }
+  __device__ static C cvt(R v) {  // f, the low half
     return __half2float(__ushort_as_half((unsigned short)v));
   }
-  __device__ static C ld(const S* p, long long i) { return cvt(ldr(p, i)); }
-  __device__ static void st(S* p, long long i, C v) {
-    gbl(reinterpret_cast<unsigned short*>(p))[i] =
-        __half_as_ushort(__float2half_rn(v));
+  __device__ static C cvt_hi(R v) {  // g, the high half
+    return __half2float(__ushort_as_half((unsigned short)(v >> 16)));
   }
 };
 
@@ -379,60 +377,84 @@ __device__ __forceinline__ void pull_raw(
       }
     }
   }
-  // the FP16 deviation form keeps the rest populations in FP32 arrays of
-  // their own (the image of a float in the 32-bit register)
-  constexpr int A0 = P == 3 ? 1 : 0;
   if constexpr (P == 3) {
+    // FP16 deviation form: one (f, g) word per direction, held in both fr
+    // and gr (cook_f takes its low half, cook_g its high half); the rest
+    // populations are an FP32 (f_0, g_0) pair per node, one 8-byte load
     const long long o = (long long)y * nx + x;
-    const Gbl<float>* r = gbl(static_cast<const float*>(p.rin));
-    fr[0] = __float_as_uint(r[o]);
-    gr[0] = __float_as_uint(r[p.N + o]);
-  }
+    const unsigned long long r =
+        gbl(static_cast<const unsigned long long*>(p.rin))[o];
+    fr[0] = (unsigned int)r;
+    gr[0] = (unsigned int)(r >> 32);
 #pragma unroll
-  for (int a = A0; a < Q; ++a) {
-    fr[a] = Tr::ldr(fin, off[a]);
-    gr[a] = Tr::ldr(gin, off[a]);
+    for (int a = 1; a < Q; ++a) fr[a] = gr[a] = Tr::ldr(fin, off[a]);
+  } else {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      fr[a] = Tr::ldr(fin, off[a]);
+      gr[a] = Tr::ldr(gin, off[a]);
+    }
   }
 }
 
-// Raw register image -> compute value of direction a (the rest population
-// of the FP16 deviation form is an FP32 image).
-template <int P>
+// Raw register image -> compute value of direction a of f (G = false) or g
+// (G = true); in the FP16 deviation form the rest population is an FP32
+// image and the others a half of the (f, g) word.
+template <int P, bool G>
 __device__ __forceinline__ typename Prec<P>::C raw_value(
     const typename Prec<P>::R v, int a) {
   if constexpr (P == 3) {
     if (a == 0) return __uint_as_float(v);
+    return G ? Prec<3>::cvt_hi(v) : Prec<3>::cvt(v);
+  } else {
+    return Prec<P>::cvt(v);
   }
-  return Prec<P>::cvt(v);
 }
 
 // Store of the nine post-collision values d[a] (storage form: deviations
 // for the shifted forms) of one node: element dix(nx, a, y, x) of buf.  The
-// FP16 deviation form stores directions 1-8 as binary16 (round to nearest
-// even) and the rest population as FP32 in rest[y nx + x], less the rounding
-// errors of the other eight: the node's stored sum is then the computed sum
-// to FP32 rounding, so biased rounding of near-constant populations does not
-// drift the mass (or sum T) of the lattice.
+// FP16 deviation form stores through half_node and store_pairs instead.
 template <int P>
-__device__ __forceinline__ void store_node(typename Prec<P>::S* buf,
-                                           float* rest, int nx, long long y,
-                                           int x,
+__device__ __forceinline__ void store_node(typename Prec<P>::S* buf, int nx,
+                                           long long y, int x,
                                            const typename Prec<P>::C d[Q]) {
-  using Tr = Prec<P>;
-  if constexpr (P == 3) {
-    float err = 0.0f;
+  static_assert(P != 3, "the FP16 deviation form stores (f, g) pairs");
 #pragma unroll
-    for (int a = 1; a < Q; ++a) {
-      const __half h = __float2half_rn(d[a]);
-      gbl(reinterpret_cast<unsigned short*>(buf))[dix(nx, a, y, x)] =
-          __half_as_ushort(h);
-      err += __half2float(h) - d[a];
-    }
-    gbl(rest)[y * nx + x] = d[0] - err;
-  } else {
+  for (int a = 0; a < Q; ++a) Prec<P>::st(buf, dix(nx, a, y, x), d[a]);
+}
+
+// FP16 deviation form, one distribution of a node: the binary16 bits of
+// d[1..8] (round to nearest even), each in the low half of h[a], and the
+// rest value d[0] less the rounding errors of the other eight, so that the
+// node's stored sum is the computed sum to FP32 rounding and biased rounding
+// of near-constant populations does not drift the mass (or sum T) of the
+// lattice.
+__device__ __forceinline__ void half_node(const float d[Q], unsigned int h[Q],
+                                          float& rest) {
+  float err = 0.0f;
 #pragma unroll
-    for (int a = 0; a < Q; ++a) Tr::st(buf, dix(nx, a, y, x), d[a]);
+  for (int a = 1; a < Q; ++a) {
+    const __half v = __float2half_rn(d[a]);
+    h[a] = __half_as_ushort(v);
+    err += __half2float(v) - d[a];
   }
+  h[0] = 0u;
+  rest = d[0] - err;
+}
+
+// FP16 deviation form: store of node (y, x), the words hf[a] | hg[a] << 16
+// of directions 1-8 into buf and the FP32 pair (rest_f, rest_g) into rest.
+__device__ __forceinline__ void store_pairs(unsigned int* buf, void* rest,
+                                            int nx, long long y, int x,
+                                            const unsigned int hf[Q],
+                                            float rest_f,
+                                            const unsigned int hg[Q],
+                                            float rest_g) {
+#pragma unroll
+  for (int a = 1; a < Q; ++a) gbl(buf)[dix(nx, a, y, x)] = hf[a] | (hg[a] << 16);
+  gbl(static_cast<unsigned long long*>(rest))[y * nx + x] =
+      (unsigned long long)__float_as_uint(rest_f) |
+      ((unsigned long long)__float_as_uint(rest_g) << 32);
 }
 
 template <int P>
@@ -442,7 +464,7 @@ __device__ __forceinline__ void cook_f(const Shift<P>& sh,
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
     if constexpr (Prec<P>::shift)
-      f[a] = raw_value<P>(fr[a], a) + sh.f(a);
+      f[a] = raw_value<P, false>(fr[a], a) + sh.f(a);
     else
       f[a] = Prec<P>::cvt(fr[a]);
   }
@@ -457,7 +479,7 @@ __device__ __forceinline__ void cook_g(const StepParams& p, const Shift<P>& sh,
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
     if constexpr (Prec<P>::shift)
-      g[a] = raw_value<P>(gr[a], a) + sh.g(a);
+      g[a] = raw_value<P, true>(gr[a], a) + sh.g(a);
     else
       g[a] = Prec<P>::cvt(gr[a]);
   }

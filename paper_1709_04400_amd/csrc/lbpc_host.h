@@ -49,8 +49,17 @@ namespace lbpc_host {
 constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
-inline size_t store_bytes(int prec) {
-  return prec == LBPC_FP64 ? 8 : (prec == LBPC_FP16_SHIFTED ? 2 : 4);
+// Bytes of the f (k = 0) or g (k = 1) populations of one buffer: nine
+// nx*ny arrays at the storage precision.  The FP16 deviation form keeps f and
+// g of a direction in one 32-bit word, all in the f array; its g pointer
+// aliases the f array.
+inline size_t dist_bytes(const lbpc_config& c, int k) {
+  const size_t n9 = 9 * (size_t)c.nx * (size_t)c.ny;
+  switch (c.precision) {
+    case LBPC_FP64: return n9 * 8;
+    case LBPC_FP16_SHIFTED: return k == 0 ? n9 * 4 : 0;
+    default: return n9 * 4;
+  }
 }
 inline size_t compute_bytes(int prec) { return prec == LBPC_FP64 ? 8 : 4; }
 // per-node history arrays (compute precision): phi(t-1), and for the BGK
@@ -59,8 +68,8 @@ inline int hist_arrays(const lbpc_config& c) {
   return c.thermal_model == LBPC_THERMAL_IMPROVED_BGK ? 3 : 1;
 }
 
-// FP32 rest populations of the FP16 deviation form, per buffer: [N] f_0,
-// then [N] g_0 (none for the other forms)
+// FP32 rest populations of the FP16 deviation form, per buffer: an
+// (f_0, g_0) pair per node, [N][2] (none for the other forms)
 inline size_t rest_bytes(const lbpc_config& c) {
   return c.precision == LBPC_FP16_SHIFTED
              ? 2 * (size_t)c.nx * (size_t)c.ny * sizeof(float)
@@ -118,13 +127,14 @@ inline void strip_shape(int nx, int bw, bool balanced, int& nbx, int& W) {
 inline Layout plan(const lbpc_config& c) {
   Layout L;
   const size_t N = (size_t)c.nx * (size_t)c.ny;
-  const size_t dbytes = align_up(9 * N * store_bytes(c.precision));
   size_t off = 0;
-  for (int b = 0; b < 2; ++b)
+  for (int b = 0; b < 2; ++b) {
     for (int k = 0; k < 2; ++k) {
       L.dist[b][k] = off;
-      off += dbytes;
+      off += align_up(dist_bytes(c, k));
     }
+    if (dist_bytes(c, 1) == 0) L.dist[b][1] = L.dist[b][0];
+  }
   for (int b = 0; b < 2; ++b) {
     L.rest[b] = off;
     off += align_up(rest_bytes(c));

@@ -199,6 +199,14 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
   }
   __shared__ C s_g[PD == 2 ? 3 : 1][PD == 2 ? Q : 1][PD == 2 ? BLOCK : 1];
   C jx1 = C(0), jy1 = C(0), tdp1 = C(0), tdp2 = C(0), irq = C(0);
+  // FP16 deviation form: f and g of a node share a word, and f* of a row
+  // is ready one iteration before g* (C1 runs a row ahead of C2), so f* waits
+  // here as binary16 bits and the corrected rest value until C2 stores the
+  // pairs
+  unsigned int hf1[Q];
+  float rf1 = 0.0f;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) hf1[a] = 0u;
   // diagnostic sums of this thread's own nodes (DIAG only)
   double d_m = 0.0, d_T = 0.0, d_e = 0.0, d_a = 0.0, d_c = 0.0, d_s = 0.0,
          d_v = 0.0, d_bad = 0.0;
@@ -217,6 +225,10 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
     const int sl1 = (it + RING - 1) % RING;   // row r - dir
     const int sl2 = (it + RING - 2) % RING;   // row r - 2 dir
     const int sl3 = (it + RING - 3) % RING;   // row r - 3 dir
+    unsigned int hfn[Q];  // f* of row r - dir (FP16 deviation form)
+    float rfn = rf1;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) hfn[a] = hf1[a];
 
     // ------------------------------------------------------------ A(r)
     C jxn = C(0), jyn = C(0), tdpn = C(0);
@@ -295,7 +307,10 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
         cook_f<P>(sh, PD == 1 ? fq1 : F[kp], fo);
 #pragma unroll
         for (int a = 0; a < Q; ++a) fo[a] -= sh.f(a);
-        store_node<P>(fout, static_cast<float*>(p.rout), nx, rb, c, fo);
+        if constexpr (P == 3)
+          half_node(fo, hfn, rfn);
+        else
+          store_node<P>(fout, nx, rb, c, fo);
       }
     } else {
       const int rb = r - dir;
@@ -388,7 +403,10 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
           from_moments(ms, fo);
 #pragma unroll
           for (int a = 0; a < Q; ++a) fo[a] -= sh.f(a);
-          store_node<P>(fout, static_cast<float*>(p.rout), nx, rb, c, fo);
+          if constexpr (P == 3)
+            half_node(fo, hfn, rfn);
+          else
+            store_node<P>(fout, nx, rb, c, fo);
         }
       }
     }
@@ -438,9 +456,14 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
 #pragma unroll
         for (int a = 0; a < Q; ++a) go[a] -= sh.g(a);
         phio[(long long)yc * nx + c] = hphi;
-        store_node<P>(gout,
-                      P == 3 ? static_cast<float*>(p.rout) + N : nullptr, nx,
-                      yc, c, go);
+        if constexpr (P == 3) {
+          unsigned int hg[Q];
+          float rg;
+          half_node(go, hg, rg);
+          store_pairs(fout, p.rout, nx, yc, c, hf1, rf1, hg, rg);
+        } else {
+          store_node<P>(gout, nx, yc, c, go);
+        }
       }
     } else {
       const int yc = r - 2 * dir;
@@ -635,9 +658,14 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
         }
 #pragma unroll
         for (int a = 0; a < Q; ++a) go[a] -= sh.g(a);
-        store_node<P>(gout,
-                      P == 3 ? static_cast<float*>(p.rout) + N : nullptr, nx,
-                      yc, c, go);
+        if constexpr (P == 3) {
+          unsigned int hg[Q];
+          float rg;
+          half_node(go, hg, rg);
+          store_pairs(fout, p.rout, nx, yc, c, hf1, rf1, hg, rg);
+        } else {
+          store_node<P>(gout, nx, yc, c, go);
+        }
         }  // !skip
       }
     }
@@ -656,6 +684,9 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
     tdp2 = tdp1;
     tdp1 = tdpn;
     irq = irn;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) hf1[a] = hfn[a];
+    rf1 = rfn;
   };
 
   if constexpr (PD == 1) {

@@ -336,7 +336,7 @@ __device__ __forceinline__ void two_step_tile(const StepParams& p, int bx,
           ts_flow(p, sf, f2b, Fo, fo);
 #pragma unroll
           for (int a = 0; a < Q; ++a) fo[a] -= sh.f(a);
-          store_node<P>(fout, nullptr, nx, rb, c, fo);
+          store_node<P>(fout, nx, rb, c, fo);
         }
       }
     }
@@ -392,7 +392,7 @@ __device__ __forceinline__ void two_step_tile(const StepParams& p, int bx,
         ts_thermal(p, sg, g2c, T, vx, vy, S0, go);
 #pragma unroll
         for (int a = 0; a < Q; ++a) go[a] -= sh.g(a);
-        store_node<P>(gout, nullptr, nx, yc, c, go);
+        store_node<P>(gout, nx, yc, c, go);
       }
     }
     __syncthreads();
