@@ -85,8 +85,9 @@ typedef enum {
  * pressure and p - rho c_s^2, and the diagnostic sums are always FP64).  The
  * shifted forms store f_a - w_a rho_ref and g_a - wg_a T_ref, with w the
  * D2Q9 weights and wg = (5/9, 1/18, ..., 1/18) the rest equilibrium of
- * Eq. (53).  LBPC_FP16_SHIFTED keeps the deviations of directions 1-8 as
- * binary16, f and g of a direction in one 32-bit word, and the rest
+ * Eq. (53).  Below FP64, f and g of a direction are stored as one (f, g)
+ * pair (8 bytes in FP32).  LBPC_FP16_SHIFTED keeps the deviations of
+ * directions 1-8 as binary16, the pair in one 32-bit word, and the rest
  * populations as an FP32 pair per node, each less the rounding errors of
  * its node's other eight. */
 typedef enum {
@@ -187,9 +188,9 @@ typedef struct lbpc_diag {
 } lbpc_diag;
 
 /* Device bytes the caller must provide for this configuration: two
- * population buffers (f and g, nine nx*ny arrays apiece at the storage
- * precision; in the FP16 deviation form nine arrays of (f, g) words and an
- * FP32 rest pair per node), two
+ * population buffers (FP64: f and g, nine nx*ny arrays apiece; below FP64
+ * nine arrays of (f, g) pairs, and in the FP16 deviation form an FP32 rest
+ * pair per node), two
  * copies of the phi history, a staging scratch of at most 40 MiB by default
  * (five FP64 fields of LBPC_STAGE_NODES nodes) and the tile list with its
  * diagnostic records. */

@@ -46,11 +46,10 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_init(StepParams p,
 #pragma unroll
   for (int a = 0; a < Q; ++a)
     d[a] = C(f[a] - (Tr::shift ? w_lat(a) * p.rho_ref : 0.0));
-  // FP16 deviation form: f waits as binary16 bits for the (f, g) pairs
+  // paired forms: f waits as its stored images for the (f, g) pairs
   unsigned int hf[Q];
-  float rf = 0.0f;
-  if constexpr (P == 3)
-    half_node(d, hf, rf);
+  if constexpr (Tr::paired)
+    pack_f<P>(d, hf);
   else
     store_node<P>(fo, p.nx, y, x, d);
   if (p.gc) {
@@ -79,14 +78,10 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_init(StepParams p,
 #pragma unroll
   for (int a = 0; a < Q; ++a)
     d[a] = C(f[a] - (Tr::shift ? w_rest(p, a) * p.T_ref : 0.0));
-  if constexpr (P == 3) {
-    unsigned int hg[Q];
-    float rg;
-    half_node(d, hg, rg);
-    store_pairs(fo, const_cast<void*>(p.rin), p.nx, y, x, hf, rf, hg, rg);
-  } else {
+  if constexpr (Tr::paired)
+    store_pairs<P>(fo, const_cast<void*>(p.rin), p.nx, y, x, hf, d);
+  else
     store_node<P>(go, p.nx, y, x, d);
-  }
 }
 
 // Fields at the current time level, computed band by band of rows (the
@@ -253,14 +248,19 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_load(StepParams p, int which,
       h[2 * o + half] = __half_as_ushort(__float2half_rn(float(in[li] - sh)));
     }
     return;
+  } else if constexpr (Tr::paired) {
+    // FP32 forms: f first, g second, in the (f, g) pair of direction a
+    const double sh = !Tr::shift ? 0.0
+                      : which < Q ? w_lat(a) * p.rho_ref
+                                  : w_rest(p, a) * p.T_ref;
+    float* w = static_cast<float*>(const_cast<void*>(p.fin));
+    w[2 * o + (which < Q ? 0 : 1)] = float(in[li] - sh);
   } else if (which < Q) {
     S* fo = static_cast<S*>(const_cast<void*>(p.fin));
-    Tr::st(fo, o,
-           typename Tr::C(in[li] - (Tr::shift ? w_lat(a) * p.rho_ref : 0.0)));
+    fo[o] = in[li];
   } else {
     S* go = static_cast<S*>(const_cast<void*>(p.gin));
-    Tr::st(go, o,
-           typename Tr::C(in[li] - (Tr::shift ? w_rest(p, a) * p.T_ref : 0.0)));
+    go[o] = in[li];
   }
 }
 

@@ -96,35 +96,39 @@ __device__ __forceinline__ Gbl<T>* gbl(T* p) { return (Gbl<T>*)p; }
 // flight across the work between its issue and its use; cvt() turns it into
 // a compute value.
 template <int P> struct Prec;
+// `paired`: f and g of a direction are stored side by side, one (f, g) word
+// per direction and node, since both stream from the same node: one access
+// per lane moves both.  FP64 keeps separate f and g arrays (the 16-byte pair
+// gained 2 % on its memory schedule, less than the registers it would cost
+// to hold f* for the pair).
 template <> struct Prec<0> {  // FP64 storage and arithmetic
   using S = double;
   using C = double;
   using R = double;
   static constexpr bool shift = false;
+  static constexpr bool paired = false;
   __device__ static R ldr(const S* p, long long i) { return gbl(p)[i]; }
   __device__ static C cvt(R v) { return v; }
   __device__ static C ld(const S* p, long long i) { return gbl(p)[i]; }
   __device__ static void st(S* p, long long i, C v) { gbl(p)[i] = v; }
 };
-template <> struct Prec<1> {  // FP32 storage and arithmetic
+// FP32 storage and arithmetic; the (f, g) pair of a direction is 8 bytes.
+template <> struct Prec<1> {
   using S = float;
   using C = float;
   using R = float;
   static constexpr bool shift = false;
-  __device__ static R ldr(const S* p, long long i) { return gbl(p)[i]; }
+  static constexpr bool paired = true;
   __device__ static C cvt(R v) { return v; }
-  __device__ static C ld(const S* p, long long i) { return gbl(p)[i]; }
-  __device__ static void st(S* p, long long i, C v) { gbl(p)[i] = v; }
 };
-template <> struct Prec<2> {  // FP32 deviations from the rest equilibrium
+// FP32 deviations from the rest equilibrium, in (f, g) pairs as FP32.
+template <> struct Prec<2> {
   using S = float;
   using C = float;
   using R = float;
   static constexpr bool shift = true;
-  __device__ static R ldr(const S* p, long long i) { return gbl(p)[i]; }
+  static constexpr bool paired = true;
   __device__ static C cvt(R v) { return v; }
-  __device__ static C ld(const S* p, long long i) { return gbl(p)[i]; }
-  __device__ static void st(S* p, long long i, C v) { gbl(p)[i] = v; }
 };
 // FP16 deviations, FP32 arithmetic.  f and g of one direction share a
 // 32-bit word (binary16 f in the low half, g in the high half): they stream
@@ -135,6 +139,7 @@ template <> struct Prec<3> {
   using C = float;
   using R = unsigned int;  // the word as loaded
   static constexpr bool shift = true;
+  static constexpr bool paired = true;
   __device__ static R ldr(const S* p, long long i) { return gbl(p)[i]; }
   __device__ static C cvt(R v) {  // f, the low half
     return __half2float(__ushort_as_half((unsigned short)v));
@@ -388,6 +393,16 @@ __device__ __forceinline__ void pull_raw(
     gr[0] = (unsigned int)(r >> 32);
 #pragma unroll
     for (int a = 1; a < Q; ++a) fr[a] = gr[a] = Tr::ldr(fin, off[a]);
+  } else if constexpr (Tr::paired) {
+    // FP32 forms: one 8-byte (f, g) pair per direction
+    const Gbl<unsigned long long>* w =
+        gbl(reinterpret_cast<const unsigned long long*>(fin));
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const unsigned long long v = w[off[a]];
+      fr[a] = __uint_as_float((unsigned int)v);
+      gr[a] = __uint_as_float((unsigned int)(v >> 32));
+    }
   } else {
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
@@ -411,16 +426,15 @@ __device__ __forceinline__ typename Prec<P>::C raw_value(
   }
 }
 
-// Store of the nine post-collision values d[a] (storage form: deviations
-// for the shifted forms) of one node: element dix(nx, a, y, x) of buf.  The
-// FP16 deviation form stores through half_node and store_pairs instead.
+// Store of the nine post-collision values d[a] of one node into separate
+// arrays (FP64): element dix(nx, a, y, x) of buf.
 template <int P>
 __device__ __forceinline__ void store_node(typename Prec<P>::S* buf, int nx,
                                            long long y, int x,
                                            const typename Prec<P>::C d[Q]) {
-  static_assert(P != 3, "the FP16 deviation form stores (f, g) pairs");
+  static_assert(!Prec<P>::paired, "paired forms store (f, g) pairs");
 #pragma unroll
-  for (int a = 0; a < Q; ++a) Prec<P>::st(buf, dix(nx, a, y, x), d[a]);
+  for (int a = 0; a < Q; ++a) gbl(buf)[dix(nx, a, y, x)] = d[a];
 }
 
 // FP16 deviation form, one distribution of a node: the binary16 bits of
@@ -438,23 +452,54 @@ __device__ __forceinline__ void half_node(const float d[Q], unsigned int h[Q],
     h[a] = __half_as_ushort(v);
     err += __half2float(v) - d[a];
   }
-  h[0] = 0u;
   rest = d[0] - err;
 }
 
-// FP16 deviation form: store of node (y, x), the words hf[a] | hg[a] << 16
-// of directions 1-8 into buf and the FP32 pair (rest_f, rest_g) into rest.
-__device__ __forceinline__ void store_pairs(unsigned int* buf, void* rest,
-                                            int nx, long long y, int x,
-                                            const unsigned int hf[Q],
-                                            float rest_f,
-                                            const unsigned int hg[Q],
-                                            float rest_g) {
+// Paired forms: f* of a node (storage form) as the 32-bit images it is
+// stored with, held until g* of the node is ready: FP32 bits, or in the
+// FP16 deviation form binary16 bits for directions 1-8 and the FP32 bits of
+// the compensated rest value for direction 0.
+template <int P>
+__device__ __forceinline__ void pack_f(const float d[Q], unsigned int h[Q]) {
+  static_assert(Prec<P>::paired, "pairs only");
+  if constexpr (P == 3) {
+    float rest;
+    half_node(d, h, rest);
+    h[0] = __float_as_uint(rest);
+  } else {
 #pragma unroll
-  for (int a = 1; a < Q; ++a) gbl(buf)[dix(nx, a, y, x)] = hf[a] | (hg[a] << 16);
-  gbl(static_cast<unsigned long long*>(rest))[y * nx + x] =
-      (unsigned long long)__float_as_uint(rest_f) |
-      ((unsigned long long)__float_as_uint(rest_g) << 32);
+    for (int a = 0; a < Q; ++a) h[a] = __float_as_uint(d[a]);
+  }
+}
+
+// Paired forms: store of node (y, x) from f* as packed by pack_f and g*
+// (storage form).  FP32: the 8-byte word f | g << 32 of each direction.
+// FP16 deviations: the word hf | hg << 16 of directions 1-8 in buf and the
+// FP32 pair (rest_f, rest_g) in rest.
+template <int P>
+__device__ __forceinline__ void store_pairs(typename Prec<P>::S* buf,
+                                            void* rest, int nx, long long y,
+                                            int x, const unsigned int hf[Q],
+                                            const float go[Q]) {
+  static_assert(Prec<P>::paired, "pairs only");
+  if constexpr (P == 3) {
+    unsigned int hg[Q];
+    float rg;
+    half_node(go, hg, rg);
+#pragma unroll
+    for (int a = 1; a < Q; ++a)
+      gbl(buf)[dix(nx, a, y, x)] = hf[a] | (hg[a] << 16);
+    gbl(static_cast<unsigned long long*>(rest))[y * nx + x] =
+        (unsigned long long)hf[0] |
+        ((unsigned long long)__float_as_uint(rg) << 32);
+  } else {
+    Gbl<unsigned long long>* w =
+        gbl(reinterpret_cast<unsigned long long*>(buf));
+#pragma unroll
+    for (int a = 0; a < Q; ++a)
+      w[dix(nx, a, y, x)] = (unsigned long long)hf[a] |
+                            ((unsigned long long)__float_as_uint(go[a]) << 32);
+  }
 }
 
 template <int P>

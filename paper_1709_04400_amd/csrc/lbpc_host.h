@@ -49,16 +49,16 @@ namespace lbpc_host {
 constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
-// Bytes of the f (k = 0) or g (k = 1) populations of one buffer: nine
-// nx*ny arrays at the storage precision.  The FP16 deviation form keeps f and
-// g of a direction in one 32-bit word, all in the f array; its g pointer
-// aliases the f array.
+// Bytes of the f (k = 0) or g (k = 1) populations of one buffer.  FP64:
+// nine nx*ny arrays each.  The other forms keep f and g of a direction as
+// one (f, g) pair (8 bytes in FP32, a 32-bit word in FP16), nine nx*ny
+// arrays of pairs, all in the f array; their g pointer aliases it.
 inline size_t dist_bytes(const lbpc_config& c, int k) {
   const size_t n9 = 9 * (size_t)c.nx * (size_t)c.ny;
   switch (c.precision) {
     case LBPC_FP64: return n9 * 8;
     case LBPC_FP16_SHIFTED: return k == 0 ? n9 * 4 : 0;
-    default: return n9 * 4;
+    default: return k == 0 ? n9 * 8 : 0;
   }
 }
 inline size_t compute_bytes(int prec) { return prec == LBPC_FP64 ? 8 : 4; }
@@ -376,12 +376,13 @@ inline int env_int(const char* name, int dflt) {
 }
 
 // Blocks of the step kernel resident per CU: the waves-per-SIMD budget the
-// kernel is compiled for (2 for FP64, 3 for the FP32 forms) over the block's
-// waves, capped by its LDS (5 rings x 5 fields, plus the g ring of the FP32
-// forms' two-row prefetch) against the CU's 160 KiB.
+// kernel is compiled for (3 for the FP16 deviation form, 2 for the others)
+// over the block's waves, capped by its LDS (5 rings x 5 fields, plus the g
+// ring of the reduced-precision forms' two-row prefetch) against the CU's
+// 160 KiB.
 inline int blocks_per_cu(int precision, int bw) {
   const bool fp64 = precision == LBPC_FP64;
-  const int by_waves = 4 * (fp64 ? 2 : 3) / (bw / 64);
+  const int by_waves = 4 * (precision == LBPC_FP16_SHIFTED ? 3 : 2) / (bw / 64);
   const int lds = fp64 ? 25 * 8 * bw : 25 * 4 * bw + 27 * 4 * bw;
   const int by_lds = 160 * 1024 / lds;
   const int n = by_waves < by_lds ? by_waves : by_lds;

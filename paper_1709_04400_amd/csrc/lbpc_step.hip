@@ -63,12 +63,17 @@ __device__ __forceinline__ void block_tile(const StepParams& p, int& bx,
   bx = b - by * p.nbx;
 }
 
-// waves per SIMD the register budget is sized for (the FP64 form holds its
-// queues of pulled values in 64-bit registers), and how many rows ahead the
-// pull runs: 1 for FP64, 2 for the FP32 forms (their g queue sits in LDS,
-// for which FP64 has no room)
+// waves per SIMD the register budget is sized for, and how many rows ahead
+// the pull runs: 1 for FP64, 2 for the reduced-precision forms (their g
+// queue sits in LDS, for which FP64 has no room).  FP64 holds its queues of
+// pulled values in 64-bit registers, and the FP32 forms hold f* of a row as
+// nine more registers until its (f, g) pairs are stored: both fit two waves
+// per SIMD.  (At three, the FP32 forms spilled; storing each side of the
+// pairs separately instead left partial writes that cost the walled
+// 256-lattice batch 37 %.)  The FP16 form's f and g share their loaded
+// registers, which leaves room for three.
 template <int P> struct StepOcc {
-  static constexpr int waves = P == 0 ? 2 : 3;
+  static constexpr int waves = P == 3 ? 3 : 2;
   static constexpr int prefetch = P == 0 ? 1 : 2;
 };
 
@@ -199,12 +204,10 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
   }
   __shared__ C s_g[PD == 2 ? 3 : 1][PD == 2 ? Q : 1][PD == 2 ? BLOCK : 1];
   C jx1 = C(0), jy1 = C(0), tdp1 = C(0), tdp2 = C(0), irq = C(0);
-  // FP16 deviation form: f and g of a node share a word, and f* of a row
-  // is ready one iteration before g* (C1 runs a row ahead of C2), so f* waits
-  // here as binary16 bits and the corrected rest value until C2 stores the
-  // pairs
+  // paired forms: f and g of a direction share a word, and f* of a row is
+  // ready one iteration before g* (C1 runs a row ahead of C2), so f* waits
+  // here as its stored images (pack_f) until C2 stores the pairs
   unsigned int hf1[Q];
-  float rf1 = 0.0f;
 #pragma unroll
   for (int a = 0; a < Q; ++a) hf1[a] = 0u;
   // diagnostic sums of this thread's own nodes (DIAG only)
@@ -225,8 +228,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
     const int sl1 = (it + RING - 1) % RING;   // row r - dir
     const int sl2 = (it + RING - 2) % RING;   // row r - 2 dir
     const int sl3 = (it + RING - 3) % RING;   // row r - 3 dir
-    unsigned int hfn[Q];  // f* of row r - dir (FP16 deviation form)
-    float rfn = rf1;
+    unsigned int hfn[Q];  // f* of row r - dir (paired forms)
 #pragma unroll
     for (int a = 0; a < Q; ++a) hfn[a] = hf1[a];
 
@@ -307,8 +309,8 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
         cook_f<P>(sh, PD == 1 ? fq1 : F[kp], fo);
 #pragma unroll
         for (int a = 0; a < Q; ++a) fo[a] -= sh.f(a);
-        if constexpr (P == 3)
-          half_node(fo, hfn, rfn);
+        if constexpr (Tr::paired)
+          pack_f<P>(fo, hfn);
         else
           store_node<P>(fout, nx, rb, c, fo);
       }
@@ -403,8 +405,8 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
           from_moments(ms, fo);
 #pragma unroll
           for (int a = 0; a < Q; ++a) fo[a] -= sh.f(a);
-          if constexpr (P == 3)
-            half_node(fo, hfn, rfn);
+          if constexpr (Tr::paired)
+            pack_f<P>(fo, hfn);
           else
             store_node<P>(fout, nx, rb, c, fo);
         }
@@ -456,14 +458,10 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
 #pragma unroll
         for (int a = 0; a < Q; ++a) go[a] -= sh.g(a);
         phio[(long long)yc * nx + c] = hphi;
-        if constexpr (P == 3) {
-          unsigned int hg[Q];
-          float rg;
-          half_node(go, hg, rg);
-          store_pairs(fout, p.rout, nx, yc, c, hf1, rf1, hg, rg);
-        } else {
+        if constexpr (Tr::paired)
+          store_pairs<P>(fout, p.rout, nx, yc, c, hf1, go);
+        else
           store_node<P>(gout, nx, yc, c, go);
-        }
       }
     } else {
       const int yc = r - 2 * dir;
@@ -658,14 +656,10 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
         }
 #pragma unroll
         for (int a = 0; a < Q; ++a) go[a] -= sh.g(a);
-        if constexpr (P == 3) {
-          unsigned int hg[Q];
-          float rg;
-          half_node(go, hg, rg);
-          store_pairs(fout, p.rout, nx, yc, c, hf1, rf1, hg, rg);
-        } else {
+        if constexpr (Tr::paired)
+          store_pairs<P>(fout, p.rout, nx, yc, c, hf1, go);
+        else
           store_node<P>(gout, nx, yc, c, go);
-        }
         }  // !skip
       }
     }
@@ -686,7 +680,6 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
     irq = irn;
 #pragma unroll
     for (int a = 0; a < Q; ++a) hf1[a] = hfn[a];
-    rf1 = rfn;
   };
 
   if constexpr (PD == 1) {

@@ -249,7 +249,6 @@ __device__ __forceinline__ void two_step_tile(const StepParams& p, int bx,
   const S* __restrict__ fin = static_cast<const S*>(p.fin);
   const S* __restrict__ gin = static_cast<const S*>(p.gin);
   S* __restrict__ fout = static_cast<S*>(p.fout);
-  S* __restrict__ gout = static_cast<S*>(p.gout);
   const Gbl<C>* __restrict__ phiv = gbl(static_cast<const C*>(p.phi));
   Gbl<C>* __restrict__ phio = gbl(static_cast<C*>(p.phi_out));
 
@@ -290,6 +289,11 @@ __device__ __forceinline__ void two_step_tile(const StepParams& p, int bx,
   C j2x_a = 0, j2y_a = 0, j2x_b = 0, j2y_b = 0;                  // step 2
   C t2a = 0, t2b = 0, t2c = 0, irq2 = 0;
   C ph1 = 0, ph2 = 0, ph3 = 0, ph4 = 0, ph5 = 0;
+  // step-2 f* of a row waits one iteration for g* of that row: the (f, g)
+  // pairs are stored together
+  unsigned int hf1[Q];
+#pragma unroll
+  for (int a = 0; a < Q; ++a) hf1[a] = 0u;
 
   pull_row(rfirst, F, G);
 
@@ -297,6 +301,9 @@ __device__ __forceinline__ void two_step_tile(const StepParams& p, int bx,
     const int r = rfirst + dir * it;
     // ring slots: a row's slot is the iteration that wrote it, mod RING
     auto sl = [&](int back) { return (it - back + 2 * RING) % RING; };
+    unsigned int hfn[Q];  // step-2 f* of row r - 6 dir
+#pragma unroll
+    for (int a = 0; a < Q; ++a) hfn[a] = hf1[a];
 
     // ---------------------------------------------------------- stage X
     C jxn = 0, jyn = 0, tdpn = 0;
@@ -336,7 +343,7 @@ __device__ __forceinline__ void two_step_tile(const StepParams& p, int bx,
           ts_flow(p, sf, f2b, Fo, fo);
 #pragma unroll
           for (int a = 0; a < Q; ++a) fo[a] -= sh.f(a);
-          store_node<P>(fout, nx, rb, c, fo);
+          pack_f<P>(fo, hfn);
         }
       }
     }
@@ -392,7 +399,7 @@ __device__ __forceinline__ void two_step_tile(const StepParams& p, int bx,
         ts_thermal(p, sg, g2c, T, vx, vy, S0, go);
 #pragma unroll
         for (int a = 0; a < Q; ++a) go[a] -= sh.g(a);
-        store_node<P>(gout, nx, yc, c, go);
+        store_pairs<P>(fout, nullptr, nx, yc, c, hf1, go);
       }
     }
     __syncthreads();
@@ -492,6 +499,8 @@ __device__ __forceinline__ void two_step_tile(const StepParams& p, int bx,
     ph3 = ph2;
     ph2 = ph1;
     ph1 = phin;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) hf1[a] = hfn[a];
   }
 }
 
