@@ -431,23 +431,24 @@ inline std::vector<std::array<int, 4>> tile_list(const StepParams& p) {
 }
 
 // Default rows per tile of a single lattice for block width bw (rows_edge:
-// the x-edge strips' runs, the same height by default).  The wave-filling
-// height of fill_rows for the device's CUs.  One exception: plain FP32
-// storage on a non-periodic
-// lattice (the boundary-capable tile kernel, 256-thread blocks, three per
-// CU) runs short tiles best.  On a 4096^2 lattice walled on all four sides:
-// FP32 28.4k MLUPS at 20 rows against 27.8k at the wave-filling 92 (16 rows
-// 28.7k, 46 rows 28.1k); FP32 deviations 27.9k at 92 against 27.2k at 20;
-// FP16 deviations 37.2k at 92 against 34.9k at 20.
+// the x-edge strips' runs, the same height by default): the wave-filling
+// height of fill_rows for the device's CUs.  One exception: the FP32 forms
+// on a non-periodic lattice (the boundary-capable tile kernel, 256-thread
+// blocks, two per CU) run best at the height whose tiles fill three waves
+// of slots exactly.  On a 4096^2 lattice walled on all four sides (17
+// strips, 512 slots): FP32 29.5k MLUPS at 46 rows (1530 tiles) against
+// 28.2k at 20, 27.6k at 38, 26.3k at 54 and 24.4k at 92; FP32 deviations
+// 29.1k at 46 against 27.7k at 20 and 24.1k at 92.  FP16 deviations (three
+// blocks per CU) run best at the one-wave height, 92 rows: 36.0k against
+// 33.6k at 20.
 inline void default_rows(const lbpc_config& c, bool tiled, int cus, int bw,
                          int& rows, int& rows_edge) {
-  if (tiled && c.precision == LBPC_FP32) {
-    rows = rows_edge = c.ny < 20 ? c.ny : 20;
-    return;
-  }
   int nbx, W;
   strip_shape(c.nx, bw, balanced_strips(c.precision, bw), nbx, W);
-  const long long slots = (long long)cus * blocks_per_cu(c.precision, bw);
+  long long slots = (long long)cus * blocks_per_cu(c.precision, bw);
+  if (tiled &&
+      (c.precision == LBPC_FP32 || c.precision == LBPC_FP32_SHIFTED))
+    slots *= 3;
   rows = rows_edge = fill_rows(c.ny, nbx, slots);
 }
 
@@ -494,8 +495,10 @@ inline bool two_step_tiles(const lbpc_config& c, bool tiled, bool graph,
 // block per CU at 2 waves per SIMD) read half the halo columns of
 // 256-thread strips: at 4096^2 FP64 +3.8 % (+3.6 % with walls), periodic
 // FP32 +5 %.  The FP32 forms on non-periodic lattices (the heavier
-// boundary-capable kernel, -11 %) and the FP16-deviation form (bound by
-// instruction issue, -16 %) need their 3 waves per SIMD and keep 256.
+// boundary-capable kernel) keep 256: walled 4096^2 FP32 ran 26.9k MLUPS at
+// 512 x 147 against 29.5k at 256 x 46.  So does the FP16-deviation form,
+// compiled for three waves per SIMD: periodic 4096^2 0.357 ms per step at
+// 256 x 92 against 0.476 at 512 x 32.
 inline void default_tiles(const lbpc_config& c, bool tiled, int cus, int& bw,
                           int& rows, int& rows_edge) {
   const bool wide = c.precision == LBPC_FP64 ||

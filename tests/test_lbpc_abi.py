@@ -105,9 +105,10 @@ def test_create_checks_workspace_and_flags():
 def test_default_tile_shapes():
     """Default tiles on a device of 256 CUs (the count assumed where none is
     visible): 4096^2 FP64 fills one wave of 256 one-block-per-CU slots with
-    9 strips of 28 runs of 147 rows, with walls on any side too; plain
-    FP32 on a walled lattice takes 20 rows, FP16 deviations the wave-filling
-    92; lbpc_set_tiles makes every strip's runs alike."""
+    9 strips of 28 runs of 147 rows, with walls on any side too; the FP32
+    forms on a walled lattice fill three waves of their 2 x 256 slots (17
+    strips x 90 runs of 46 rows = 1530 tiles), FP16 deviations one wave of
+    3 x 256; lbpc_set_tiles makes every strip's runs alike."""
     lb = _lbpc()
     W, P = I.BC_WALL, I.BC_PERIODIC
 
@@ -123,9 +124,10 @@ def test_default_tile_shapes():
         h, got = shape(bc)
         lb.lbpc_destroy(h)
         assert got == want, (bc, got)
-    h, got = shape([W] * 4, I.FP32)
-    lb.lbpc_destroy(h)
-    assert got == (256, 20, 20)
+    for prec in (I.FP32, I.FP32_SHIFTED):
+        h, got = shape([W] * 4, prec)
+        lb.lbpc_destroy(h)
+        assert got == (256, 46, 46), (prec, got)
     # FP16 deviations: 17 strips of 252 columns x 45 runs of 92 rows = 765
     # tiles in one wave of 3 x 256 slots
     h, got = shape([W] * 4, I.FP16_SHIFTED)
