@@ -486,9 +486,11 @@ __device__ __forceinline__ void store_pairs(typename Prec<P>::S* buf,
     unsigned int hg[Q];
     float rg;
     half_node(go, hg, rg);
+    // one byte permute per word: the low halves of hf[a] and hg[a]
 #pragma unroll
     for (int a = 1; a < Q; ++a)
-      gbl(buf)[dix(nx, a, y, x)] = hf[a] | (hg[a] << 16);
+      gbl(buf)[dix(nx, a, y, x)] =
+          __builtin_amdgcn_perm(hg[a], hf[a], 0x05040100u);
     gbl(static_cast<unsigned long long*>(rest))[y * nx + x] =
         (unsigned long long)hf[0] |
         ((unsigned long long)__float_as_uint(rg) << 32);
