@@ -33,11 +33,16 @@ PREC_NAME = {0: "FP64", 1: "FP32", 2: "FP32_SHIFTED", 3: "FP16_SHIFTED"}
 PREC_DTYPE = {0: "f64", 1: "f32", 2: "f32", 3: "f16+f32-storage/f32"}
 
 
-def gpu_run(n, prec, steps, warmup, per_launch=40, model=0):
+def gpu_run(n, prec, steps, warmup, per_launch=40, model=0, walls=False):
     import torch
     from paper_1709_04400_amd import inputs, lbpc
     cfg, fl = inputs.spinodal(n, precision=prec)
     cfg["thermal_model"] = model
+    if walls:
+        # no-slip walls on all four sides (the boundary-capable tile-list
+        # kernel); a timing workload only: its state turns invalid after
+        # 400-500 steps, so it is timed over fewer
+        cfg["bc"] = [inputs.BC_WALL] * 4
     sim = lbpc.Simulation(cfg)
     sim.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
     del fl
@@ -423,6 +428,14 @@ def main():
                 var[name] = {"error": str(e)}
                 continue
             var[name] = entry(vms, vk, bpl, "f64")
+        # the same workload walled on all four sides, every form, default
+        # tiles of the boundary-capable kernel
+        for prec in (0, 1, 2, 3):
+            vms, vk, vcfg = gpu_run(args.n, prec, 100, 10, per_launch=20,
+                                    walls=True)
+            e = entry(vms, vk, BYTES_PER_LUP[prec], PREC_DTYPE[prec])
+            e["tiles"] = vcfg["tiles"]
+            var["WALLED_" + PREC_NAME[prec]] = e
         out["variants"] = var
     if args.batch:
         bsteps = max(args.steps // 10, 50)
