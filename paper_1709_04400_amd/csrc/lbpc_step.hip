@@ -83,10 +83,38 @@ template <int P> struct StepOcc {
 // liquid area, count above the mid density, sum S0, max |v|^2, non-finite.
 constexpr int DIAG_VALS = 8;
 
+// Side and hot-spot temperatures of the stencil ghosts, in the compute type.
+// HOLD: read once into registers.  FP64 needs that: with the parameter loads
+// inside the row loop its compiler turned "ghost ? load of T_side : stencil
+// value" into one load through a selected pointer, which moved stencil values
+// into scratch memory on every row (16 B written per node).  The FP32 forms
+// read them in place, as written at their use: any other form of the same
+// reads cost the FP16 form's boundary-capable kernel four more spilled
+// registers and 21 % on a walled lattice.
+template <class C, bool HOLD> struct SideTemps;
+template <class C> struct SideTemps<C, true> {
+  C t[4], th;
+  __device__ explicit SideTemps(const StepParams& p) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t[i] = C(p.T_bc[i]);
+    th = C(p.T_hot);
+  }
+  __device__ C side(int i) const { return t[i]; }
+  __device__ C hot() const { return th; }
+};
+template <class C> struct SideTemps<C, false> {
+  __device__ explicit SideTemps(const StepParams&) {}
+};
+
 // PROBE: the same loads and stores in the same schedule with the
 // arithmetic left out (each node stores the values it pulled, phi its
 // history): the memory time of the step's access pattern.
-template <int P, bool GEN, int BLOCK, bool DIAG, bool PROBE = false>
+// MRT: the lattice runs one of the MRT thermal models (improved or
+// compromised), so the Gong-Cheng and BGK-form branches are compiled out;
+// the FP16-deviation form, bound by instruction issue, takes this
+// instantiation (3 % faster at 4096^2, 73 -> 32 spilled scalar registers).
+template <int P, bool GEN, int BLOCK, bool DIAG, bool PROBE = false,
+          bool MRT = false>
 __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
                                           int slot, double* __restrict__ dpart,
                                           bool nostore) {
@@ -204,6 +232,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
   }
   __shared__ C s_g[PD == 2 ? 3 : 1][PD == 2 ? Q : 1][PD == 2 ? BLOCK : 1];
   C jx1 = C(0), jy1 = C(0), tdp1 = C(0), tdp2 = C(0), irq = C(0);
+  const SideTemps<C, GEN && P == 0> stemp(p);
   // paired forms: f and g of a direction share a word, and f* of a row is
   // ready one iteration before g* (C1 runs a row ahead of C2), so f* waits
   // here as its stored images (pack_f) until C2 stores the pairs
@@ -420,10 +449,10 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
     {
       const int yc = r - 2 * dir;
       if (doC && yc >= Y0 && yc < Y1 && p.phi_valid &&
-          (p.improved || p.bgk)) {
+          (p.improved || (!MRT && p.bgk))) {
         const long long o = (long long)yc * nx + c;
         hphi = phiv[o];
-        if (p.bgk) {
+        if ((!MRT && p.bgk)) {
           htx = phiv[N + o];
           hty = phiv[2 * N + o];
         }
@@ -522,11 +551,20 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
               if (ox) col = c;
               else if (col < 0) col += nx;
               else if (col >= nx) col -= nx;
-              const C Ty = ys == 2 ? (col >= p.hot_x0 && col < p.hot_x1
-                                          ? C(p.T_hot)
-                                          : C(p.T_bc[2]))
-                                   : C(p.T_bc[3]);
-              const C Tg = oy ? Ty : C(p.T_bc[xs]);
+              C Tg;
+              if constexpr (P == 0 && GEN) {
+                const C Ty = ys == 2 ? (col >= p.hot_x0 && col < p.hot_x1
+                                            ? stemp.hot()
+                                            : stemp.side(2))
+                                     : stemp.side(3);
+                Tg = oy ? Ty : stemp.side(xs);
+              } else {
+                const C Ty = ys == 2 ? (col >= p.hot_x0 && col < p.hot_x1
+                                            ? C(p.T_hot)
+                                            : C(p.T_bc[2]))
+                                     : C(p.T_bc[3]);
+                Tg = oy ? Ty : C(p.T_bc[xs]);
+              }
               Tn[k] = (ox || oy) ? Tg : Tn[k];
               vxn[k] = wall ? C(0) : vxn[k];
               vyn[k] = wall ? C(0) : vyn[k];
@@ -550,7 +588,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
         // phi of Eq. (28): div(lambda grad T)/(rho c_V) - k lap T
         //                  + (T - T (dp/dT)/(rho c_V)) div v
         C phi;
-        if (p.gc) {
+        if ((!MRT && p.gc)) {
           // Eq. (13): T (1 - (dp/dT)/(rho c_V)) div v
           phi = (T - tdp2 * irq * C(p.inv_cv)) * divv;
         } else {
@@ -570,7 +608,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
         }
         const long long o = (long long)yc * nx + c;
         C S0 = phi;
-        if (p.improved || p.bgk) {
+        if (p.improved || (!MRT && p.bgk)) {
           const C prev = p.phi_valid ? hphi : phi;
           S0 = phi + C(0.5) * (phi - prev);
         }
@@ -600,14 +638,14 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
 #pragma unroll
           for (int a = 0; a < Q; ++a) gb[a] = s_g[k2][a][t];
         }
-        if (p.gc || p.bgk) {
+        if ((!MRT && p.gc) || (!MRT && p.bgk)) {
           // BGK collisions.  Gong-Cheng, Eq. (12): g^eq of Eq. (14), source
           // omega_a phi, tau_g = lambda/(rho c_V c_s^2) + 1/2.  BGK form of
           // the improved model, Eq. (33): g^eq of Eq. (29), source
           // omega_a S0 (Eq. 32) and the correction of Eq. (31) with
           // d_t(T v) = T v(t) - T v(t-1) (history after phi in the array)
           C itau, base, q2, src, cf = C(0), dx = C(0), dy = C(0);
-          if (p.gc) {
+          if ((!MRT && p.gc)) {
             itau = recip(C(p.gc_ta) * irq + C(p.gc_tb));
             base = C(1) - C(1.5) * (vx * vx + vy * vy);
             q2 = C(4.5);
@@ -735,14 +773,14 @@ template <int P, int BLOCK> struct BlockOcc {
   static constexpr int waves = BLOCK == 512 ? 2 : StepOcc<P>::waves;
 };
 
-template <int P, bool GEN, int BLOCK, bool DIAG>
+template <int P, bool GEN, int BLOCK, bool DIAG, bool MRT = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(
     BlockOcc<P, BLOCK>::waves, BlockOcc<P, BLOCK>::waves))) void
 k_step(StepParams p, double* dpart, int nostore) {
   int bx, by;
   block_tile(p, bx, by);
-  step_tile<P, GEN, BLOCK, DIAG>(p, bx, by, by * p.nbx + bx, dpart,
-                                 nostore != 0);
+  step_tile<P, GEN, BLOCK, DIAG, false, MRT>(p, bx, by, by * p.nbx + bx,
+                                             dpart, nostore != 0);
 }
 
 // The memory schedule of k_step without its arithmetic (see step_tile):
@@ -810,28 +848,36 @@ hipError_t launch_step(const StepParams& p, int prec, hipStream_t s,
   const bool gen = !(p.perx && p.pery);
   // lattices with a non-periodic side run the tile-list kernel
   if (gen) return hipErrorInvalidValue;
-#define LBPC_LAUNCH_BW(PR, BW)                                              \
-  if (dpart)                                                                \
-    hipLaunchKernelGGL((k_step<PR, false, BW, true>), grid, dim3(BW), 0, s, \
-                       p, dpart, nostore);                                  \
-  else                                                                      \
-    hipLaunchKernelGGL((k_step<PR, false, BW, false>), grid, dim3(BW), 0,   \
+#define LBPC_LAUNCH_BW(PR, BW, M)                                              \
+  if (dpart)                                                                   \
+    hipLaunchKernelGGL((k_step<PR, false, BW, true, M>), grid, dim3(BW), 0, s, \
+                       p, dpart, nostore);                                     \
+  else                                                                         \
+    hipLaunchKernelGGL((k_step<PR, false, BW, false, M>), grid, dim3(BW), 0,   \
                        s, p, dpart, 0);
-#define LBPC_LAUNCH(PR)                                                     \
-  if (p.bw == 64) {                                                         \
-    LBPC_LAUNCH_BW(PR, 64)                                                  \
-  } else if (p.bw == 128) {                                                 \
-    LBPC_LAUNCH_BW(PR, 128)                                                 \
-  } else if (p.bw == 512) {                                                 \
-    LBPC_LAUNCH_BW(PR, 512)                                                 \
-  } else {                                                                  \
-    LBPC_LAUNCH_BW(PR, 256)                                                 \
+#define LBPC_LAUNCH(PR, M)                                                     \
+  if (p.bw == 64) {                                                            \
+    LBPC_LAUNCH_BW(PR, 64, M)                                                  \
+  } else if (p.bw == 128) {                                                    \
+    LBPC_LAUNCH_BW(PR, 128, M)                                                 \
+  } else if (p.bw == 512) {                                                    \
+    LBPC_LAUNCH_BW(PR, 512, M)                                                 \
+  } else {                                                                     \
+    LBPC_LAUNCH_BW(PR, 256, M)                                                 \
   }
   switch (prec) {
-    case 0: LBPC_LAUNCH(0); break;
-    case 1: LBPC_LAUNCH(1); break;
-    case 2: LBPC_LAUNCH(2); break;
-    case 3: LBPC_LAUNCH(3); break;
+    case 0: LBPC_LAUNCH(0, false); break;
+    case 1: LBPC_LAUNCH(1, false); break;
+    case 2: LBPC_LAUNCH(2, false); break;
+    case 3:
+      // the FP16-deviation form under an MRT thermal model takes the
+      // instantiation without the Gong-Cheng and BGK-form branches
+      if (!p.gc && !p.bgk) {
+        LBPC_LAUNCH(3, true);
+      } else {
+        LBPC_LAUNCH(3, false);
+      }
+      break;
     default: return hipErrorInvalidValue;
   }
 #undef LBPC_LAUNCH
