@@ -495,12 +495,18 @@ def read_traffic(path, n):
 
 
 def _kernel_hash():
+    """Hash of the code (comments and layout left out) of the step kernel's
+    sources and of the host code that picks its tile shape."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in ("lbpc_step.hip", "lbpc_device.h", "lbpc_host.h"):
         with open(os.path.join(ROOT, "paper_1709_04400_amd", "csrc",
-                               name), "rb") as f:
-            h.update(f.read())
+                               name)) as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -3,10 +3,13 @@
 // One launch performs one whole time step (pull-streaming, moments, EOS,
 // force, velocity, thermal source, both MRT collisions, store).  Layout and
 // schedule:
-//   * each distribution buffer interleaves the rows of its nine direction
-//     arrays, [ny][9][nx]; two buffers per distribution, ping-pong.  The
-//     kernel reads post-collision f*(t-1), g*(t-1) (or pre-collision f(t),
-//     g(t) right after an initialisation: "fresh") and writes f*(t), g*(t);
+//   * each buffer interleaves the rows of its nine direction arrays,
+//     [ny][9][nx]; two buffers, ping-pong.  FP64 keeps f and g in buffers of
+//     their own; the other forms store f and g of a direction as one pair
+//     (8 bytes in FP32, a 32-bit word of two binary16 in the FP16 form, whose
+//     rest populations are an FP32 pair per node).  The kernel reads
+//     post-collision f*(t-1), g*(t-1) (or pre-collision f(t), g(t) right
+//     after an initialisation: "fresh") and writes f*(t), g*(t);
 //   * a block of BLOCK threads (64 to 512: one to eight wave64) owns a strip
 //     of at most BLOCK - 4 columns plus 2 halo columns per side (one column
 //     per thread) and a run of H rows, and marches along the rows (up or
@@ -14,12 +17,14 @@
 //       A(r)   rho, j, T of row r from its pulled f, g; EOS (FP64): psi and
 //              T (dp/dT)_rho -> LDS rings (5 rows) / registers
 //       B(r-1) interaction force from psi rows r-2..r, buoyancy, velocity
-//              -> LDS ring; flow MRT collision of row r-1, store f*
+//              -> LDS ring; flow MRT collision of row r-1, store f* (the
+//              paired forms hold f* one iteration, to store it with g*)
 //       pull of the next row(s) issued here, in flight during C2
 //       C(r-2) isotropic differences of T, v (and rho) on rows r-3..r-1,
 //              thermal source phi, S0, improved thermal MRT collision of
 //              row r-2 (or a BGK collision: the Gong-Cheng model, or the
-//              BGK form of the improved model), store g*, phi
+//              BGK form of the improved model), store g* (with f* in the
+//              paired forms), phi
 //     so every pulled value is loaded from memory once per block (halo
 //     columns and the 4 warm-up rows aside) and the 2-hop stencil dependence
 //     (div v needs v one node away, which needs psi two nodes away) never
