@@ -190,10 +190,9 @@ typedef struct lbpc_diag {
 /* Device bytes the caller must provide for this configuration: two
  * population buffers (FP64: f and g, nine nx*ny arrays apiece; below FP64
  * nine arrays of (f, g) pairs, and in the FP16 deviation form an FP32 rest
- * pair per node), two
- * copies of the phi history, a staging scratch of at most 40 MiB by default
- * (five FP64 fields of LBPC_STAGE_NODES nodes) and the tile list with its
- * diagnostic records. */
+ * pair per node), two copies of the phi history, a staging scratch of at
+ * most 40 MiB by default (five FP64 fields of LBPC_STAGE_NODES nodes) and
+ * the tile list with its diagnostic records. */
 lbpc_status lbpc_workspace_bytes(const lbpc_config *cfg, size_t *bytes);
 
 /* Validates cfg and binds the workspace and stream (hipStream_t, may be
@@ -233,9 +232,9 @@ lbpc_status lbpc_step(lbpc_handle *h, int64_t n);
  * the strip is at most that many columns minus 4 halo columns) and rows per
  * tile (>= 4), the same for every strip.  Results do not depend on it.
  * Default: 512 for FP64 and for the periodic FP32 forms, 256 otherwise;
- * rows: 20 for plain FP32 on a lattice with a non-periodic side, otherwise
- * the height that makes the tile count just fill a whole number of waves
- * of resident blocks. */
+ * rows: the height that makes the tile count just fill a whole number of
+ * waves of resident blocks (for the FP32 forms on a lattice with a
+ * non-periodic side: three waves). */
 lbpc_status lbpc_set_tiles(lbpc_handle *h, int32_t block_width, int32_t rows);
 
 /* The tile shape in place: threads per block, rows per tile, and rows per
