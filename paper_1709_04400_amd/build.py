@@ -23,7 +23,8 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
+    # the sources compile concurrently (the step kernels' file dominates)
+    objs, procs = [], []
     for src in SOURCES:
         obj = os.path.join(CSRC, "_build", src + ".o")
         os.makedirs(os.path.dirname(obj), exist_ok=True)
@@ -32,8 +33,11 @@ def build(verbose: bool = False) -> str:
                                         obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        procs.append((cmd, subprocess.Popen(cmd)))
         objs.append(obj)
+    failed = [cmd for cmd, proc in procs if proc.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
