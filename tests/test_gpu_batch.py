@@ -60,10 +60,13 @@ def test_every_lattice_matches_the_oracle(bw, rows):
     b.close()
 
 
-def test_fp32_batch_equals_single_handles_bitwise():
-    """Every lattice of an FP32 batch is bitwise the same lattice run alone
-    (the arithmetic of a node does not depend on the tiling)."""
-    cases = I.batch_cases(count=5, seed=11, precision=I.FP32)
+@pytest.mark.parametrize("prec", [I.FP32, I.FP32_SHIFTED, I.FP16_SHIFTED])
+def test_batch_equals_single_handles_bitwise(prec):
+    """Every lattice of a batch is bitwise the same lattice run alone (the
+    arithmetic of a node does not depend on the tiling), in each storage form
+    whose (f, g) pairs and rest arrays the batch lays out per lattice."""
+    print(f"\n[batch] batch vs single handles precision={prec}", flush=True)
+    cases = I.batch_cases(count=5, seed=11, precision=prec)
     b = _batch(cases)
     b.step(60)
     for k, (cfg, f) in enumerate(cases):
