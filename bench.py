@@ -26,11 +26,14 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per lattice update: 9 f + 9 g read and written, plus the
 # phi history read and written (storage bytes / phi bytes per precision)
 BYTES_PER_LUP = {0: 36 * 8 + 2 * 8, 1: 36 * 4 + 2 * 4, 2: 36 * 4 + 2 * 4,
-                 3: 32 * 2 + 4 * 4 + 2 * 4}
+                 3: 32 * 2 + 4 * 4 + 2 * 4, 4: 32 * 2 + 4 * 4 + 2 * 4 + 2 * 4}
 # (FP16 deviations: the 8 moving populations of f and g in binary16, the
-# rest populations f_0, g_0 in FP32, and phi)
-PREC_NAME = {0: "FP64", 1: "FP32", 2: "FP32_SHIFTED", 3: "FP16_SHIFTED"}
-PREC_DTYPE = {0: "f64", 1: "f32", 2: "f32", 3: "f16+f32-storage/f32"}
+# rest populations f_0, g_0 in FP32, and phi; node-local references: also
+# each node's reference word, read and written)
+PREC_NAME = {0: "FP64", 1: "FP32", 2: "FP32_SHIFTED", 3: "FP16_SHIFTED",
+             4: "FP16_LOCAL"}
+PREC_DTYPE = {0: "f64", 1: "f32", 2: "f32", 3: "f16+f32-storage/f32",
+              4: "f16+f32-storage/f32"}
 
 
 def gpu_run(n, prec, steps, warmup, per_launch=40, model=0, walls=False):
@@ -390,7 +393,7 @@ def main():
                 e["hbm_bytes_per_lup"] = bpl / spl
                 e["hbm_GBs"] = round(vb / spl, 1)
             return e
-        for prec in (1, 2, 3):
+        for prec in (1, 2, 3, 4):
             vms, vk, vcfg = gpu_run(args.n, prec, max(args.steps // 4, 50),
                                     args.warmup)
             var[PREC_NAME[prec]] = entry(vms, vk, BYTES_PER_LUP[prec],
@@ -430,7 +433,7 @@ def main():
             var[name] = entry(vms, vk, bpl, "f64")
         # the same workload walled on all four sides, every form, default
         # tiles of the boundary-capable kernel
-        for prec in (0, 1, 2, 3):
+        for prec in (0, 1, 2, 3, 4):
             vms, vk, vcfg = gpu_run(args.n, prec, 100, 10, per_launch=20,
                                     walls=True)
             e = entry(vms, vk, BYTES_PER_LUP[prec], PREC_DTYPE[prec])

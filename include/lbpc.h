@@ -89,12 +89,20 @@ typedef enum {
  * pair (8 bytes in FP32).  LBPC_FP16_SHIFTED keeps the deviations of
  * directions 1-8 as binary16, the pair in one 32-bit word, and the rest
  * populations as an FP32 pair per node, each less the rounding errors of
- * its node's other eight. */
+ * its node's other eight.  LBPC_FP16_LOCAL stores the same words against
+ * node-local references instead of rho_ref and T_ref: each node keeps a
+ * binary16 (rho, T) of its own in its direction-0 word, and the value a
+ * node sends in direction a is stored less w_a rho and wg_a T of the node
+ * that will pull it (x + e_a; itself across a wall), so binary16 holds only
+ * the velocity and non-equilibrium parts; the rest populations are FP32
+ * full values (96 bytes moved per node and step against 88).  The
+ * reference fields of lbpc_config are not used by it. */
 typedef enum {
   LBPC_FP64 = 0,
   LBPC_FP32 = 1,
   LBPC_FP32_SHIFTED = 2,
-  LBPC_FP16_SHIFTED = 3
+  LBPC_FP16_SHIFTED = 3,
+  LBPC_FP16_LOCAL = 4
 } lbpc_precision;
 
 /* side kinds; sides are ordered x-, x+, y-, y+.  Opposite sides are both
@@ -313,7 +321,12 @@ lbpc_status lbpc_step_diag(lbpc_handle *h, int64_t n, lbpc_diag *out);
  * as FP64 (for the BGK form of the improved model followed by T v_x and
  * T v_y of step t-1, [ny][nx] each), then phi_valid, rho_ave and step as
  * three 8-byte words: lbpc_state_bytes gives the host buffer size.  Save
- * waits for the stream and refuses (LBPC_ERR_NUMERIC) a flagged state. */
+ * waits for the stream and refuses (LBPC_ERR_NUMERIC) a flagged state.  A
+ * loaded state resumes the run bit for bit, except in LBPC_FP16_LOCAL,
+ * whose node references are not part of it: a load stores each value
+ * against a reference taken from its node's rest populations (rho_ref =
+ * f_0 / w_0, T_ref = g_0 / wg_0), which changes the first step's values by
+ * their binary16 rounding. */
 lbpc_status lbpc_state_bytes(const lbpc_handle *h, size_t *bytes);
 lbpc_status lbpc_save_state(lbpc_handle *h, void *host, size_t bytes);
 lbpc_status lbpc_load_state(lbpc_handle *h, const void *host, size_t bytes);

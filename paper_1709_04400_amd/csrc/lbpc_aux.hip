@@ -46,12 +46,17 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_init(StepParams p,
 #pragma unroll
   for (int a = 0; a < Q; ++a)
     d[a] = C(f[a] - (Tr::shift ? w_lat(a) * p.rho_ref : 0.0));
-  // paired forms: f waits as its stored images for the (f, g) pairs
+  // paired forms: f waits as its stored images for the (f, g) pairs (FP32
+  // in the node-referenced FP16 form, which packs f and g together)
   unsigned int hf[Q];
-  if constexpr (Tr::paired)
+  if constexpr (P == 4) {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) hf[a] = __float_as_uint(d[a]);
+  } else if constexpr (Tr::paired) {
     pack_f<P>(d, hf);
-  else
+  } else {
     store_node<P>(fo, p.nx, y, x, d);
+  }
   if (p.gc) {
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
@@ -78,7 +83,19 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_init(StepParams p,
 #pragma unroll
   for (int a = 0; a < Q; ++a)
     d[a] = C(f[a] - (Tr::shift ? w_rest(p, a) * p.T_ref : 0.0));
-  if constexpr (Tr::paired)
+  if constexpr (P == 4) {
+    // every value against the node's own reference: in the layout an
+    // initialisation leaves, each node pulls its own values
+    float fv[Q], rr[Q], tr[Q];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      fv[a] = __uint_as_float(hf[a]);
+      rr[a] = ref_round(float(rho));
+      tr[a] = ref_round(float(T));
+    }
+    store_local(p, fo, const_cast<void*>(p.rin), p.nx, y, x, fv, d, rr, tr,
+                ref_word(float(rho), float(T)));
+  } else if constexpr (Tr::paired)
     store_pairs<P>(fo, const_cast<void*>(p.rin), p.nx, y, x, hf, d);
   else
     store_node<P>(go, p.nx, y, x, d);
@@ -219,7 +236,10 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_canon(StepParams p, int which,
 }
 
 // FP64 canonical direction `which` of the nodes [i0, i0 + cnt), held in
-// in[0 .. cnt) -> storage buffer (fresh layout)
+// in[0 .. cnt) -> storage buffer (fresh layout).  The node-referenced FP16
+// form needs each node's reference before its directions 1-8: the rest
+// populations, which the host loads first (which = 0 before 1-8, 9 before
+// 10-17), give it, rho_ref = f_0 / w_0 and T_ref = g_0 / wg_0 in binary16.
 template <int P>
 __global__ __launch_bounds__(AUX_BLOCK) void k_load(StepParams p, int which,
                                                     const double* in,
@@ -246,6 +266,22 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_load(StepParams p, int which,
       unsigned short* h =
           static_cast<unsigned short*>(const_cast<void*>(p.fin));
       h[2 * o + half] = __half_as_ushort(__float2half_rn(float(in[li] - sh)));
+    }
+    return;
+  } else if constexpr (P == 4) {
+    const int half = which < Q ? 0 : 1;
+    unsigned short* h = static_cast<unsigned short*>(const_cast<void*>(p.fin));
+    const long long o0 = dix(p.nx, 0, y, (int)(i - y * p.nx));
+    if (a == 0) {
+      float* rest = static_cast<float*>(const_cast<void*>(p.rin));
+      rest[2 * i + half] = float(in[li]);
+      const double w0 = which < Q ? w_lat(0) : w_rest(p, 0);
+      h[2 * o0 + half] = __half_as_ushort(__float2half_rn(float(in[li] / w0)));
+    } else {
+      const float ref = __half2float(__ushort_as_half(h[2 * o0 + half]));
+      const float wr = which < Q ? float(w_lat(a)) * ref
+                                 : float(w_rest(p, a)) * ref;
+      h[2 * o + half] = __half_as_ushort(__float2half_rn(float(in[li]) - wr));
     }
     return;
   } else if constexpr (Tr::paired) {
@@ -294,6 +330,7 @@ static inline unsigned nblocks(long long N) {
     case 1: X(1); break;          \
     case 2: X(2); break;          \
     case 3: X(3); break;          \
+    case 4: X(4); break;          \
     default: return hipErrorInvalidValue; \
   }
 

@@ -148,6 +148,39 @@ template <> struct Prec<3> {
     return __half2float(__ushort_as_half((unsigned short)(v >> 16)));
   }
 };
+// FP16 deviations from node-local references, FP32 arithmetic.  Every node
+// keeps a reference word in its direction-0 slot: binary16 rho_ref (low
+// half) and T_ref (high half), the density and temperature it had when the
+// word was stored.  The (f, g) word of direction a of node x holds
+// f*_a - w_a rho_ref and g*_a - wg_a T_ref against the reference of the node
+// that pulls it: x + e_a, or x itself where e_a crosses a wall.  A puller
+// then adds its own reference (one 4-byte load per node) and the stored
+// values are the velocity and non-equilibrium parts only, which binary16
+// resolves in the liquid as finely as in the vapour.  The rest populations
+// are FP32 full values.  (Across an open side the clamped source's value
+// was stored against its interior neighbour's reference, which the puller
+// reads there.)
+template <> struct Prec<4> {
+  using S = unsigned int;
+  using C = float;
+  using R = unsigned int;
+  static constexpr bool shift = false;
+  static constexpr bool paired = true;
+  __device__ static R ldr(const S* p, long long i) { return gbl(p)[i]; }
+  __device__ static C cvt(R v) {
+    return __half2float(__ushort_as_half((unsigned short)v));
+  }
+  __device__ static C cvt_hi(R v) {
+    return __half2float(__ushort_as_half((unsigned short)(v >> 16)));
+  }
+};
+
+// reference word of the node-referenced FP16 form: binary16 rho | T << 16
+// (round to nearest even)
+__device__ __forceinline__ unsigned int ref_word(float rho, float T) {
+  return (unsigned int)__half_as_ushort(__float2half_rn(rho)) |
+         ((unsigned int)__half_as_ushort(__float2half_rn(T)) << 16);
+}
 
 // D2Q9 weights (shift of f, Eq. 14) and the rest equilibrium of g of the
 // lattice's thermal model (side rules and shift of g)
@@ -393,6 +426,21 @@ __device__ __forceinline__ void pull_raw(
     gr[0] = (unsigned int)(r >> 32);
 #pragma unroll
     for (int a = 1; a < Q; ++a) fr[a] = gr[a] = Tr::ldr(fin, off[a]);
+  } else if constexpr (P == 4) {
+    // node-referenced FP16 form: the (f, g) words in fr, the rest pair in
+    // fr[0] / gr[0], and in gr[1..8] the reference the values were stored
+    // against: the node's own (cook_f replaces it across an open side)
+    const long long o = (long long)y * nx + x;
+    const unsigned long long r =
+        gbl(static_cast<const unsigned long long*>(p.rin))[o];
+    fr[0] = (unsigned int)r;
+    gr[0] = (unsigned int)(r >> 32);
+    const unsigned int own = Tr::ldr(fin, dix(nx, 0, y, x));
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+      fr[a] = Tr::ldr(fin, off[a]);
+      gr[a] = own;
+    }
   } else if constexpr (Tr::paired) {
     // FP32 forms: one 8-byte (f, g) pair per direction
     const Gbl<unsigned long long>* w =
@@ -472,6 +520,63 @@ __device__ __forceinline__ void pack_f(const float d[Q], unsigned int h[Q]) {
   }
 }
 
+// Node-referenced FP16 form: as half_node, with the value of direction a
+// taken relative to r[a] (its reference times its weight).
+__device__ __forceinline__ void half_node_ref(const float d[Q],
+                                              const float r[Q],
+                                              unsigned int h[Q],
+                                              float& rest) {
+  float err = 0.0f;
+#pragma unroll
+  for (int a = 1; a < Q; ++a) {
+    const float dv = d[a] - r[a];
+    const __half v = __float2half_rn(dv);
+    h[a] = __half_as_ushort(v);
+    err += __half2float(v) - dv;
+  }
+  rest = d[0] - err;
+}
+
+// binary16 rounding of a reference value, as the puller reads it back
+__device__ __forceinline__ float ref_round(float v) {
+  return __half2float(__float2half_rn(v));
+}
+
+// Node-referenced FP16 form: store of node (y, x) from f* and g* (FP32):
+// its own reference word `own` into direction 0, the (f, g) words of
+// directions 1-8, f*_a less w_a rr[a] and g*_a less wg_a tr[a] (rr, tr:
+// rho_ref and T_ref of the node that pulls value a, binary16 values), and
+// the FP32 rest pair, each rest value less the rounding errors of the
+// node's other eight.
+__device__ __forceinline__ void store_local(const StepParams& p,
+                                            unsigned int* buf, void* rest,
+                                            int nx, long long y, int x,
+                                            const float fo[Q],
+                                            const float go[Q],
+                                            const float rr[Q],
+                                            const float tr[Q],
+                                            unsigned int own) {
+  float wr[Q], wt[Q];
+  wr[0] = wt[0] = 0.0f;
+#pragma unroll
+  for (int a = 1; a < Q; ++a) {
+    wr[a] = float(w_lat(a)) * rr[a];
+    wt[a] = float(w_rest(p, a)) * tr[a];
+  }
+  unsigned int hf[Q], hg[Q];
+  float rf, rg;
+  half_node_ref(fo, wr, hf, rf);
+  half_node_ref(go, wt, hg, rg);
+  gbl(buf)[dix(nx, 0, y, x)] = own;
+#pragma unroll
+  for (int a = 1; a < Q; ++a)
+    gbl(buf)[dix(nx, a, y, x)] =
+        __builtin_amdgcn_perm(hg[a], hf[a], 0x05040100u);
+  gbl(static_cast<unsigned long long*>(rest))[y * nx + x] =
+      (unsigned long long)__float_as_uint(rf) |
+      ((unsigned long long)__float_as_uint(rg) << 32);
+}
+
 // Paired forms: store of node (y, x) from f* as packed by pack_f and g*
 // (storage form).  FP32: the 8-byte word f | g << 32 of each direction.
 // FP16 deviations: the word hf | hg << 16 of directions 1-8 in buf and the
@@ -504,31 +609,70 @@ __device__ __forceinline__ void store_pairs(typename Prec<P>::S* buf,
   }
 }
 
-template <int P>
-__device__ __forceinline__ void cook_f(const Shift<P>& sh,
+template <int P, bool GEN>
+__device__ __forceinline__ void cook_f(const StepParams& p, const Shift<P>& sh,
+                                       int x, int y,
                                        const typename Prec<P>::R fr[Q],
+                                       const typename Prec<P>::R gr[Q],
                                        typename Prec<P>::C f[Q]) {
+  if constexpr (P == 4) {
+    f[0] = __uint_as_float(fr[0]);
 #pragma unroll
-  for (int a = 0; a < Q; ++a) {
-    if constexpr (Prec<P>::shift)
-      f[a] = raw_value<P, false>(fr[a], a) + sh.f(a);
-    else
-      f[a] = Prec<P>::cvt(fr[a]);
+    for (int a = 1; a < Q; ++a)
+      f[a] = Prec<4>::cvt(fr[a]) + float(w_lat(a)) * Prec<4>::cvt(gr[a]);
+    if (GEN && !p.fresh) {
+      // across an open side the value comes from the clamped source, whose
+      // puller is its neighbour x + e_a inside the lattice: the value was
+      // stored against that node's reference, read here (waves with an
+      // edge node only)
+      const EdgeSides e(p, x, y, true);
+      if (__builtin_amdgcn_ballot_w64(e.any()) != 0) {
+        const Gbl<unsigned int>* w = gbl(static_cast<const unsigned int*>(p.fin));
+#pragma unroll
+        for (int a = 1; a < Q; ++a) {
+          const bool ox = e.ox(a), oy = e.oy(a);
+          if ((ox || oy) && !e.wall(p, a)) {
+            int xd = ox ? x + EXs[a] : x, yd = oy ? y + EYs[a] : y;
+            xd = xd < 0 ? 0 : (xd >= p.nx ? p.nx - 1 : xd);
+            yd = yd < 0 ? 0 : (yd >= p.ny ? p.ny - 1 : yd);
+            f[a] = Prec<4>::cvt(fr[a]) +
+                   float(w_lat(a)) * Prec<4>::cvt(w[dix(p.nx, 0, yd, xd)]);
+          }
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      if constexpr (Prec<P>::shift)
+        f[a] = raw_value<P, false>(fr[a], a) + sh.f(a);
+      else
+        f[a] = Prec<P>::cvt(fr[a]);
+    }
   }
 }
 
 template <int P, bool GEN>
 __device__ __forceinline__ void cook_g(const StepParams& p, const Shift<P>& sh,
                                        int x, int y,
+                                       const typename Prec<P>::R fr[Q],
                                        const typename Prec<P>::R gr[Q],
                                        typename Prec<P>::C g[Q]) {
   using C = typename Prec<P>::C;
+  if constexpr (P == 4) {
+    g[0] = __uint_as_float(gr[0]);
 #pragma unroll
-  for (int a = 0; a < Q; ++a) {
-    if constexpr (Prec<P>::shift)
-      g[a] = raw_value<P, true>(gr[a], a) + sh.g(a);
-    else
-      g[a] = Prec<P>::cvt(gr[a]);
+    for (int a = 1; a < Q; ++a)
+      g[a] = Prec<4>::cvt_hi(fr[a]) +
+             float(w_rest(p, a)) * Prec<4>::cvt_hi(gr[a]);
+  } else {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      if constexpr (Prec<P>::shift)
+        g[a] = raw_value<P, true>(gr[a], a) + sh.g(a);
+      else
+        g[a] = Prec<P>::cvt(gr[a]);
+    }
   }
   if (GEN && !p.fresh) {
     const EdgeSides e(p, x, y, true);
@@ -576,8 +720,8 @@ __device__ __forceinline__ void pull_node(
     typename Prec<P>::C fn[Q], typename Prec<P>::C gn[Q]) {
   typename Prec<P>::R fr[Q], gr[Q];
   pull_raw<P, GEN>(p, fin, gin, x, y, fr, gr);
-  cook_f<P>(sh, fr, fn);
-  cook_g<P, GEN>(p, sh, x, y, gr, gn);
+  cook_f<P, GEN>(p, sh, x, y, fr, gr, fn);
+  cook_g<P, GEN>(p, sh, x, y, fr, gr, gn);
 }
 
 // ------------------------------------------------------- MRT transforms

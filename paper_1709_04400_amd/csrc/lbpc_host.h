@@ -53,11 +53,15 @@ inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 // nine nx*ny arrays each.  The other forms keep f and g of a direction as
 // one (f, g) pair (8 bytes in FP32, a 32-bit word in FP16), nine nx*ny
 // arrays of pairs, all in the f array; their g pointer aliases it.
+inline bool fp16_form(int prec) {
+  return prec == LBPC_FP16_SHIFTED || prec == LBPC_FP16_LOCAL;
+}
 inline size_t dist_bytes(const lbpc_config& c, int k) {
   const size_t n9 = 9 * (size_t)c.nx * (size_t)c.ny;
   switch (c.precision) {
     case LBPC_FP64: return n9 * 8;
-    case LBPC_FP16_SHIFTED: return k == 0 ? n9 * 4 : 0;
+    case LBPC_FP16_SHIFTED:
+    case LBPC_FP16_LOCAL: return k == 0 ? n9 * 4 : 0;
     default: return k == 0 ? n9 * 8 : 0;
   }
 }
@@ -68,10 +72,10 @@ inline int hist_arrays(const lbpc_config& c) {
   return c.thermal_model == LBPC_THERMAL_IMPROVED_BGK ? 3 : 1;
 }
 
-// FP32 rest populations of the FP16 deviation form, per buffer: an
-// (f_0, g_0) pair per node, [N][2] (none for the other forms)
+// FP32 rest populations of the FP16 forms, per buffer: an (f_0, g_0) pair
+// per node, [N][2] (none for the other forms)
 inline size_t rest_bytes(const lbpc_config& c) {
-  return c.precision == LBPC_FP16_SHIFTED
+  return fp16_form(c.precision)
              ? 2 * (size_t)c.nx * (size_t)c.ny * sizeof(float)
              : 0;
 }
@@ -208,7 +212,7 @@ inline const char* check_config(const lbpc_config* c) {
   if (c->thermal_model == LBPC_THERMAL_GONG_CHENG &&
       !(c->lambda_mode == LBPC_LAMBDA_CONST ? c->lambda0 > 0.0 : c->chi > 0.0))
     return "the Gong-Cheng model needs lambda0 > 0 or chi > 0";
-  if (c->precision < LBPC_FP64 || c->precision > LBPC_FP16_SHIFTED)
+  if (c->precision < LBPC_FP64 || c->precision > LBPC_FP16_LOCAL)
     return "unknown precision";
   return nullptr;
 }
@@ -358,7 +362,7 @@ inline int tile_grid(int nwork, int prec, int bw) {
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
                                 dev);
-  const int waves = prec == LBPC_FP64 ? 2 : 3;
+  const int waves = fp16_form(prec) ? 3 : 2;
   int per_cu = 4 * waves / (bw / 64);
   if (per_cu < 1) per_cu = 1;
   return nwork < cus * per_cu ? nwork : cus * per_cu;
@@ -376,13 +380,12 @@ inline int env_int(const char* name, int dflt) {
 }
 
 // Blocks of the step kernel resident per CU: the waves-per-SIMD budget the
-// kernel is compiled for (3 for the FP16 deviation form, 2 for the others)
-// over the block's waves, capped by its LDS (5 rings x 5 fields, plus the g
-// ring of the reduced-precision forms' two-row prefetch) against the CU's
-// 160 KiB.
+// kernel is compiled for (3 for the FP16 forms, 2 for the others) over the
+// block's waves, capped by its LDS (5 rings x 5 fields, plus the g ring of
+// the reduced-precision forms' two-row prefetch) against the CU's 160 KiB.
 inline int blocks_per_cu(int precision, int bw) {
   const bool fp64 = precision == LBPC_FP64;
-  const int by_waves = 4 * (precision == LBPC_FP16_SHIFTED ? 3 : 2) / (bw / 64);
+  const int by_waves = 4 * (fp16_form(precision) ? 3 : 2) / (bw / 64);
   const int lds = fp64 ? 25 * 8 * bw : 25 * 4 * bw + 27 * 4 * bw;
   const int by_lds = 160 * 1024 / lds;
   const int n = by_waves < by_lds ? by_waves : by_lds;
@@ -502,7 +505,7 @@ inline bool two_step_tiles(const lbpc_config& c, bool tiled, bool graph,
 inline void default_tiles(const lbpc_config& c, bool tiled, int cus, int& bw,
                           int& rows, int& rows_edge) {
   const bool wide = c.precision == LBPC_FP64 ||
-                    (c.precision != LBPC_FP16_SHIFTED && !tiled);
+                    (!fp16_form(c.precision) && !tiled);
   bw = env_int("LBPC_TILE_BW", wide ? 512 : 256);
   if (!valid_block_width(bw)) bw = 256;
   // runs shorter than 4 rows are not supported (the tile list and its

@@ -75,10 +75,10 @@ __device__ __forceinline__ void block_tile(const StepParams& p, int& bx,
 // nine more registers until its (f, g) pairs are stored: both fit two waves
 // per SIMD.  (At three, the FP32 forms spilled; storing each side of the
 // pairs separately instead left partial writes that cost the walled
-// 256-lattice batch 37 %.)  The FP16 form's f and g share their loaded
+// 256-lattice batch 37 %.)  The FP16 forms' f and g share their loaded
 // registers, which leaves room for three.
 template <int P> struct StepOcc {
-  static constexpr int waves = P == 3 ? 3 : 2;
+  static constexpr int waves = P >= 3 ? 3 : 2;
   static constexpr int prefetch = P == 0 ? 1 : 2;
 };
 
@@ -183,6 +183,34 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
     sg[a] = C(p.s_g[a]);
   }
 
+  // node-referenced FP16 form: binary16 rho and T of the nodes that pull
+  // the eight values node (x, y) stores, x + e_a, from the LDS rings (s0,
+  // sU, sD: slots of rows y, y + 1, y - 1, clamped like the stencil's), or
+  // the node's own where e_a leaves the lattice across a wall (a value
+  // leaving across an open side is never pulled); rr[0], tr[0] are its own.
+  auto dest_refs = [&](int s0, int sU, int sD, int x, int y, float rr[Q],
+                       float tr[Q]) __attribute__((always_inline)) {
+    constexpr int SLOT[Q] = {0, 0, 1, 0, 2, 1, 1, 2, 2};  // y, y+1, y-1
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const int sl = SLOT[a] == 0 ? s0 : (SLOT[a] == 1 ? sU : sD);
+      const int tt = EXs[a] > 0 ? ttp : (EXs[a] < 0 ? ttm : t);
+      rr[a] = ref_round(s_rho[sl][tt]);
+      tr[a] = ref_round(s_T[sl][tt]);
+    }
+    if (GEN) {
+      const EdgeSides e(p, x, y, true);
+      if (__builtin_amdgcn_ballot_w64(e.any()) != 0) {
+#pragma unroll
+        for (int a = 1; a < Q; ++a)
+          if (e.wall(p, OPs[a])) {
+            rr[a] = rr[0];
+            tr[a] = tr[0];
+          }
+      }
+    }
+  };
+
   // row r -> wrapped row, or -1 for a ghost row of a non-periodic y side
   auto wrap_row = [&](int r) -> int {
     if (r >= 0 && r < ny) return r;
@@ -271,8 +299,8 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
     const int rwA = wrap_row(r);
     if (doA && rwA >= 0) {
       C fa[Q], ga[Q];
-      cook_f<P>(sh, F[k], fa);
-      cook_g<P, GEN>(p, sh, cw, rwA, G[k], ga);
+      cook_f<P, GEN>(p, sh, cw, rwA, F[k], G[k], fa);
+      cook_g<P, GEN>(p, sh, cw, rwA, F[k], G[k], ga);
       if constexpr (PD == 2) {
 #pragma unroll
         for (int a = 0; a < Q; ++a) s_g[k][a][t] = ga[a];
@@ -340,13 +368,18 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
       const int rb = r - dir;
       if (doC && rb >= Y0 && rb < Y1) {
         C fo[Q];
-        cook_f<P>(sh, PD == 1 ? fq1 : F[kp], fo);
+        cook_f<P, GEN>(p, sh, c, rb, PD == 1 ? fq1 : F[kp],
+                       PD == 1 ? fq1 : G[kp], fo);
 #pragma unroll
         for (int a = 0; a < Q; ++a) fo[a] -= sh.f(a);
-        if constexpr (Tr::paired)
+        if constexpr (P == 4) {
+#pragma unroll
+          for (int a = 0; a < Q; ++a) hfn[a] = __float_as_uint(fo[a]);
+        } else if constexpr (Tr::paired) {
           pack_f<P>(fo, hfn);
-        else
+        } else {
           store_node<P>(fout, nx, rb, c, fo);
+        }
       }
     } else {
       const int rb = r - dir;
@@ -407,7 +440,8 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
           // flow MRT collision with the forcing scheme of the flow model;
           // |F_m|^2 / psi^2 = G^2 (sx^2 + sy^2), folded into sig1, sig2
           C m[Q], ms[Q], fo[Q], fb[Q];
-          cook_f<P>(sh, PD == 1 ? fq1 : F[kp], fb);
+          cook_f<P, GEN>(p, sh, c, rb, PD == 1 ? fq1 : F[kp],
+                         PD == 1 ? fq1 : G[kp], fb);
           to_moments(fb, m);
           const C v2 = vx * vx + vy * vy;
           C meq[Q];
@@ -439,10 +473,15 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
           from_moments(ms, fo);
 #pragma unroll
           for (int a = 0; a < Q; ++a) fo[a] -= sh.f(a);
-          if constexpr (Tr::paired)
+          if constexpr (P == 4) {
+            // f* waits in FP32: its references are taken with g*'s at C2
+#pragma unroll
+            for (int a = 0; a < Q; ++a) hfn[a] = __float_as_uint(fo[a]);
+          } else if constexpr (Tr::paired) {
             pack_f<P>(fo, hfn);
-          else
+          } else {
             store_node<P>(fout, nx, rb, c, fo);
+          }
         }
       }
     }
@@ -484,7 +523,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
       if (doC && yc >= Y0 && yc < Y1) {
         C go[Q];
         if constexpr (PD == 1) {
-          cook_g<P, GEN>(p, sh, c, yc, gq2, go);
+          cook_g<P, GEN>(p, sh, c, yc, gq2, gq2, go);
         } else {
 #pragma unroll
           for (int a = 0; a < Q; ++a) go[a] = s_g[k2][a][t];
@@ -492,10 +531,18 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
 #pragma unroll
         for (int a = 0; a < Q; ++a) go[a] -= sh.g(a);
         phio[(long long)yc * nx + c] = hphi;
-        if constexpr (Tr::paired)
+        if constexpr (P == 4) {
+          // (the values stored are not used)
+          float fo[Q];
+          const float z[Q] = {};
+#pragma unroll
+          for (int a = 0; a < Q; ++a) fo[a] = __uint_as_float(hf1[a]);
+          store_local(p, fout, p.rout, nx, yc, c, fo, go, z, z, 0u);
+        } else if constexpr (Tr::paired) {
           store_pairs<P>(fout, p.rout, nx, yc, c, hf1, go);
-        else
+        } else {
           store_node<P>(gout, nx, yc, c, go);
+        }
       }
     } else {
       const int yc = r - 2 * dir;
@@ -638,7 +685,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
         phio[o] = phi;
         C go[Q], gb[Q];
         if constexpr (PD == 1) {
-          cook_g<P, GEN>(p, sh, c, yc, gq2, gb);
+          cook_g<P, GEN>(p, sh, c, yc, gq2, gq2, gb);
         } else {
 #pragma unroll
           for (int a = 0; a < Q; ++a) gb[a] = s_g[k2][a][t];
@@ -699,10 +746,18 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
         }
 #pragma unroll
         for (int a = 0; a < Q; ++a) go[a] -= sh.g(a);
-        if constexpr (Tr::paired)
+        if constexpr (P == 4) {
+          float fo[Q], rr[Q], tr[Q];
+#pragma unroll
+          for (int a = 0; a < Q; ++a) fo[a] = __uint_as_float(hf1[a]);
+          dest_refs(sl2, sN, sS, c, yc, rr, tr);
+          store_local(p, fout, p.rout, nx, yc, c, fo, go, rr, tr,
+                      ref_word(s_rho[sl2][t], T));
+        } else if constexpr (Tr::paired) {
           store_pairs<P>(fout, p.rout, nx, yc, c, hf1, go);
-        else
+        } else {
           store_node<P>(gout, nx, yc, c, go);
+        }
         }  // !skip
       }
     }
@@ -813,6 +868,7 @@ hipError_t launch_step_probe(const StepParams& p, int prec, hipStream_t s) {
     case 1: LBPC_PROBE_BW(1); break;
     case 2: LBPC_PROBE_BW(2); break;
     case 3: LBPC_PROBE_BW(3); break;
+    case 4: LBPC_PROBE_BW(4); break;
     default: return hipErrorInvalidValue;
   }
 #undef LBPC_PROBE_BW
@@ -875,12 +931,19 @@ hipError_t launch_step(const StepParams& p, int prec, hipStream_t s,
     case 1: LBPC_LAUNCH(1, false); break;
     case 2: LBPC_LAUNCH(2, false); break;
     case 3:
-      // the FP16-deviation form under an MRT thermal model takes the
-      // instantiation without the Gong-Cheng and BGK-form branches
+      // the FP16 forms under an MRT thermal model take the instantiation
+      // without the Gong-Cheng and BGK-form branches
       if (!p.gc && !p.bgk) {
         LBPC_LAUNCH(3, true);
       } else {
         LBPC_LAUNCH(3, false);
+      }
+      break;
+    case 4:
+      if (!p.gc && !p.bgk) {
+        LBPC_LAUNCH(4, true);
+      } else {
+        LBPC_LAUNCH(4, false);
       }
       break;
     default: return hipErrorInvalidValue;
@@ -927,6 +990,7 @@ hipError_t launch_step_batch(const StepParams* table, const void* work,
     case 1: LBPC_BLAUNCH(1); break;
     case 2: LBPC_BLAUNCH(2); break;
     case 3: LBPC_BLAUNCH(3); break;
+    case 4: LBPC_BLAUNCH(4); break;
     default: return hipErrorInvalidValue;
   }
 #undef LBPC_BLAUNCH

@@ -309,8 +309,8 @@ __device__ __forceinline__ void two_step_tile(const StepParams& p, int bx,
     C jxn = 0, jyn = 0, tdpn = 0;
     if (doA1 && in_rows(r, 5)) {                  // step-1 A(r)
       C fa[Q], ga[Q];
-      cook_f<P>(sh, F, fa);
-      cook_g<P, false>(p, sh, cw, wrap_row(r), G, ga);
+      cook_f<P, false>(p, sh, cw, wrap_row(r), F, G, fa);
+      cook_g<P, false>(p, sh, cw, wrap_row(r), F, G, ga);
       const C sa = fa[1] + fa[2] + fa[3] + fa[4];
       const C sd = fa[5] + fa[6] + fa[7] + fa[8];
       const C rho = fa[0] + sa + sd;
@@ -362,7 +362,7 @@ __device__ __forceinline__ void two_step_tile(const StepParams& p, int bx,
         a_vy[sl(1)][t] = Fo.vy;
         if (doC1 && in_rows(rb, 3)) {
           C fb[Q], fo[Q];
-          cook_f<P>(sh, fq1, fb);
+          cook_f<P, false>(p, sh, cw, wrap_row(rb), fq1, fq1, fb);
           ts_flow(p, sf, fb, Fo, fo);
           // f*(t) of row r - dir into its LDS row (storage form)
 #pragma unroll
@@ -420,7 +420,7 @@ __device__ __forceinline__ void two_step_tile(const StepParams& p, int bx,
         }
         phin = phi;
         C gb[Q], go[Q];
-        cook_g<P, false>(p, sh, c, yc, gq2, gb);
+        cook_g<P, false>(p, sh, c, yc, gq2, gq2, gb);
         ts_thermal(p, sg, gb, T, vx, vy, S0, go);
 #pragma unroll
         for (int a = 0; a < Q; ++a)

@@ -32,7 +32,7 @@ BC_PERIODIC, BC_WALL, BC_OPEN = 0, 1, 2
 LAMBDA_CONST, LAMBDA_RHO_CV_CHI = 0, 1
 THERMAL_IMPROVED, THERMAL_COMPROMISED, THERMAL_GONG_CHENG = 0, 1, 2
 THERMAL_IMPROVED_BGK = 3
-FP64, FP32, FP32_SHIFTED, FP16_SHIFTED = 0, 1, 2, 3
+FP64, FP32, FP32_SHIFTED, FP16_SHIFTED, FP16_LOCAL = 0, 1, 2, 3, 4
 
 # kinematic viscosity nu = 0.1 (Sec. IV.A) -> s_nu = 1 / (3 nu + 1/2)
 NU = 0.1

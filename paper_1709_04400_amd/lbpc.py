@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "liblbpc.so")
 
 OK, ERR_ARG, ERR_HIP, ERR_OOM, ERR_STATE, ERR_NUMERIC, ERR_UNSUPPORTED = (
     0, -1, -2, -3, -4, -5, -6)
-FP64, FP32, FP32_SHIFTED, FP16_SHIFTED = 0, 1, 2, 3
+FP64, FP32, FP32_SHIFTED, FP16_SHIFTED, FP16_LOCAL = 0, 1, 2, 3, 4
 
 # every entry point declared in include/lbpc.h
 EXPORTS = (

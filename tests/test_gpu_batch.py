@@ -60,7 +60,8 @@ def test_every_lattice_matches_the_oracle(bw, rows):
     b.close()
 
 
-@pytest.mark.parametrize("prec", [I.FP32, I.FP32_SHIFTED, I.FP16_SHIFTED])
+@pytest.mark.parametrize("prec", [I.FP32, I.FP32_SHIFTED, I.FP16_SHIFTED,
+                                  I.FP16_LOCAL])
 def test_batch_equals_single_handles_bitwise(prec):
     """Every lattice of a batch is bitwise the same lattice run alone (the
     arithmetic of a node does not depend on the tiling), in each storage form

@@ -79,10 +79,12 @@ def test_smallest_box_hot_spot_wetting_variable_conductivity():
 
 
 # the short-run bounds of the other reduced-precision parity tests
-SHORT = {I.FP32: 3e-5, I.FP32_SHIFTED: 3e-5, I.FP16_SHIFTED: 2e-2}
+SHORT = {I.FP32: 3e-5, I.FP32_SHIFTED: 3e-5, I.FP16_SHIFTED: 2e-2,
+         I.FP16_LOCAL: 2e-3}
 
 
-@pytest.mark.parametrize("prec", [I.FP32, I.FP32_SHIFTED, I.FP16_SHIFTED])
+@pytest.mark.parametrize("prec", [I.FP32, I.FP32_SHIFTED, I.FP16_SHIFTED,
+                                  I.FP16_LOCAL])
 @pytest.mark.parametrize("sides", ["periodic", "walls"])
 def test_smallest_lattice_reduced_precision(prec, sides):
     cfg, fl = _cut(4, 4, sides)
@@ -209,7 +211,8 @@ def test_default_tiles_on_a_wide_walled_lattice():
     g.close()
 
 
-@pytest.mark.parametrize("prec", [I.FP32, I.FP32_SHIFTED, I.FP16_SHIFTED])
+@pytest.mark.parametrize("prec", [I.FP32, I.FP32_SHIFTED, I.FP16_SHIFTED,
+                                  I.FP16_LOCAL])
 @pytest.mark.parametrize("bc", [[OP, OP, W, W], [OP] * 4])
 def test_open_x_sides_reduced_precision(prec, bc):
     """The FP32 forms' short edge path for rows away from the y sides also

@@ -154,7 +154,7 @@ def _twice(cfg, fl, steps):
 
 
 @pytest.mark.parametrize("prec", [I.FP64, I.FP32, I.FP32_SHIFTED,
-                                  I.FP16_SHIFTED])
+                                  I.FP16_SHIFTED, I.FP16_LOCAL])
 @pytest.mark.parametrize("sides", ["periodic", "walls"])
 def test_run_twice_is_bitwise_identical(prec, sides):
     cfg, fl = I.bubble(nx=300, ny=96, pool=60, hot_width=20, g=3e-5,

@@ -30,9 +30,9 @@ CENTRES = [(0, 0), (241, 35), (252, 70), (4095, 4095), (3856, 4095),
 # measured when they were set (FP64 6.5e-16; FP32 1.4e-7, FP32 deviations
 # 1.5e-7, FP16 deviations 2.2e-4; mass drift 1e-15, 9e-9, 9e-9, 7.8e-7)
 TOL = {I.FP64: 1e-12, I.FP32: 5e-7, I.FP32_SHIFTED: 5e-7,
-       I.FP16_SHIFTED: 7e-4}
+       I.FP16_SHIFTED: 7e-4, I.FP16_LOCAL: 7e-4}
 MASS = {I.FP64: 1e-12, I.FP32: 3e-8, I.FP32_SHIFTED: 3e-8,
-        I.FP16_SHIFTED: 3e-6}
+        I.FP16_SHIFTED: 3e-6, I.FP16_LOCAL: 3e-6}
 
 
 def _split(state):
@@ -53,7 +53,7 @@ def _window(a, cx, cy):
 
 
 @pytest.mark.parametrize("prec", [I.FP64, I.FP32, I.FP32_SHIFTED,
-                                  I.FP16_SHIFTED])
+                                  I.FP16_SHIFTED, I.FP16_LOCAL])
 def test_spinodal_4096_one_step_in_windows(prec):
     from paper_1709_04400_amd import lbpc
     cfg, fl = I.spinodal(N, precision=prec)
@@ -139,7 +139,7 @@ def _cut_window(a, x0, y0):
 
 
 @pytest.mark.parametrize("prec", [I.FP64, I.FP32, I.FP32_SHIFTED,
-                                  I.FP16_SHIFTED])
+                                  I.FP16_SHIFTED, I.FP16_LOCAL])
 def test_walled_4096_in_windows(prec):
     """The 4096 x 4096 spinodal walled on all four sides.  FP64 with the two
     x-edge strips on 137-row runs and the others on 147-row runs (one wave);

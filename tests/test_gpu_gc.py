@@ -87,10 +87,12 @@ def test_gc_in_a_batch_with_other_models():
 
 
 # bounds about three times the errors measured when they were set
-GC_SHORT = {I.FP32: 3e-5, I.FP32_SHIFTED: 3e-5, I.FP16_SHIFTED: 2e-2}
+GC_SHORT = {I.FP32: 3e-5, I.FP32_SHIFTED: 3e-5, I.FP16_SHIFTED: 2e-2,
+            I.FP16_LOCAL: 2e-3}
 
 
-@pytest.mark.parametrize("prec", [I.FP32, I.FP32_SHIFTED, I.FP16_SHIFTED])
+@pytest.mark.parametrize("prec", [I.FP32, I.FP32_SHIFTED, I.FP16_SHIFTED,
+                                  I.FP16_LOCAL])
 def test_gc_reduced_precision_short_run(prec):
     cfg, fl = I.heated_droplet(64, 14.0, 1.1)
     cfg["thermal_model"] = GC

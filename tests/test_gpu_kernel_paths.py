@@ -22,7 +22,9 @@ def _lb():
                                         (I.FP32, I.THERMAL_IMPROVED),
                                         (I.FP32_SHIFTED, I.THERMAL_IMPROVED),
                                         (I.FP16_SHIFTED, I.THERMAL_IMPROVED),
-                                        (I.FP16_SHIFTED, I.THERMAL_GONG_CHENG)])
+                                        (I.FP16_SHIFTED, I.THERMAL_GONG_CHENG),
+                                        (I.FP16_LOCAL, I.THERMAL_IMPROVED),
+                                        (I.FP16_LOCAL, I.THERMAL_GONG_CHENG)])
 def test_periodic_kernel_equals_tile_list_kernel(prec, model):
     """The periodic step kernel (for the FP16 form under an MRT thermal
     model, its instantiation without the Gong-Cheng and BGK branches) and

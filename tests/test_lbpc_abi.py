@@ -70,6 +70,10 @@ def test_workspace_bytes_and_validation():
     assert n >= 4 * 9 * 100 * 100 * 8 + 100 * 100 * 8
     cfg16 = dict(cfg, precision=I.FP16_SHIFTED)
     assert lb.lbpc_workspace_bytes(cfg16) < n
+    # node-local references: the same (f, g) words and rest pairs (the
+    # reference word sits in the unused direction-0 slot)
+    assert lb.lbpc_workspace_bytes(dict(cfg, precision=I.FP16_LOCAL)) == \
+        lb.lbpc_workspace_bytes(cfg16)
     # too small, more than 2^31 nodes, unpaired periodic side, ...
     bad = [dict(cfg, nx=3), dict(cfg, ny=3), dict(cfg, nx=65536, ny=32769),
            dict(cfg, bc=[0, 1, 0, 0]), dict(cfg, G=1.0),
@@ -128,11 +132,12 @@ def test_default_tile_shapes():
         h, got = shape([W] * 4, prec)
         lb.lbpc_destroy(h)
         assert got == (256, 46, 46), (prec, got)
-    # FP16 deviations: 17 strips of 252 columns x 45 runs of 92 rows = 765
+    # FP16 forms: 17 strips of 252 columns x 45 runs of 92 rows = 765
     # tiles in one wave of 3 x 256 slots
-    h, got = shape([W] * 4, I.FP16_SHIFTED)
-    lb.lbpc_destroy(h)
-    assert got == (256, 92, 92)
+    for prec in (I.FP16_SHIFTED, I.FP16_LOCAL):
+        h, got = shape([W] * 4, prec)
+        lb.lbpc_destroy(h)
+        assert got == (256, 92, 92), (prec, got)
     h, _ = shape([W] * 4)
     lb._check(lb.lib().lbpc_set_tiles(h, 256, 24), h)
     t = lb.lbpc_get_tiles(h)
