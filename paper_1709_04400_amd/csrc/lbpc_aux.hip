@@ -46,12 +46,19 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_init(StepParams p,
 #pragma unroll
   for (int a = 0; a < Q; ++a)
     d[a] = C(f[a] - (Tr::shift ? w_lat(a) * p.rho_ref : 0.0));
-  // paired forms: f waits as its stored images for the (f, g) pairs (FP32
-  // in the node-referenced FP16 form, which packs f and g together)
+  // paired forms: f waits as its stored images for the (f, g) pairs; the
+  // node-referenced FP16 form stores every value against the node's own
+  // reference (in the layout an initialisation leaves, each node pulls its
+  // own values)
   unsigned int hf[Q];
-  if constexpr (P == 4) {
+  float rr[Q], tr[Q];
 #pragma unroll
-    for (int a = 0; a < Q; ++a) hf[a] = __float_as_uint(d[a]);
+  for (int a = 0; a < Q; ++a) {
+    rr[a] = ref_round(float(rho));
+    tr[a] = ref_round(float(T));
+  }
+  if constexpr (P == 4) {
+    pack_f_local(d, rr, hf);
   } else if constexpr (Tr::paired) {
     pack_f<P>(d, hf);
   } else {
@@ -83,19 +90,10 @@ __global__ __launch_bounds__(AUX_BLOCK) void k_init(StepParams p,
 #pragma unroll
   for (int a = 0; a < Q; ++a)
     d[a] = C(f[a] - (Tr::shift ? w_rest(p, a) * p.T_ref : 0.0));
-  if constexpr (P == 4) {
-    // every value against the node's own reference: in the layout an
-    // initialisation leaves, each node pulls its own values
-    float fv[Q], rr[Q], tr[Q];
-#pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      fv[a] = __uint_as_float(hf[a]);
-      rr[a] = ref_round(float(rho));
-      tr[a] = ref_round(float(T));
-    }
-    store_local(p, fo, const_cast<void*>(p.rin), p.nx, y, x, fv, d, rr, tr,
-                ref_word(float(rho), float(T)));
-  } else if constexpr (Tr::paired)
+  if constexpr (P == 4)
+    store_pairs_local(p, fo, const_cast<void*>(p.rin), p.nx, y, x, hf, d, tr,
+                      ref_word(float(rho), float(T)));
+  else if constexpr (Tr::paired)
     store_pairs<P>(fo, const_cast<void*>(p.rin), p.nx, y, x, hf, d);
   else
     store_node<P>(go, p.nx, y, x, d);

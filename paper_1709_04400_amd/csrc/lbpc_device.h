@@ -542,30 +542,35 @@ __device__ __forceinline__ float ref_round(float v) {
   return __half2float(__float2half_rn(v));
 }
 
-// Node-referenced FP16 form: store of node (y, x) from f* and g* (FP32):
-// its own reference word `own` into direction 0, the (f, g) words of
-// directions 1-8, f*_a less w_a rr[a] and g*_a less wg_a tr[a] (rr, tr:
-// rho_ref and T_ref of the node that pulls value a, binary16 values), and
-// the FP32 rest pair, each rest value less the rounding errors of the
-// node's other eight.
-__device__ __forceinline__ void store_local(const StepParams& p,
-                                            unsigned int* buf, void* rest,
-                                            int nx, long long y, int x,
-                                            const float fo[Q],
-                                            const float go[Q],
-                                            const float rr[Q],
-                                            const float tr[Q],
-                                            unsigned int own) {
-  float wr[Q], wt[Q];
-  wr[0] = wt[0] = 0.0f;
+// Node-referenced FP16 form: f* of a node as the images it is stored with
+// (as pack_f), each direction a >= 1 less w_a rr[a], rr[a] the rho_ref
+// (a binary16 value) of the node that pulls it.
+__device__ __forceinline__ void pack_f_local(const float d[Q],
+                                             const float rr[Q],
+                                             unsigned int h[Q]) {
+  float wr[Q];
+  wr[0] = 0.0f;
 #pragma unroll
-  for (int a = 1; a < Q; ++a) {
-    wr[a] = float(w_lat(a)) * rr[a];
-    wt[a] = float(w_rest(p, a)) * tr[a];
-  }
-  unsigned int hf[Q], hg[Q];
-  float rf, rg;
-  half_node_ref(fo, wr, hf, rf);
+  for (int a = 1; a < Q; ++a) wr[a] = float(w_lat(a)) * rr[a];
+  float rest;
+  half_node_ref(d, wr, h, rest);
+  h[0] = __float_as_uint(rest);
+}
+
+// Node-referenced FP16 form: store of node (y, x) from f* as packed by
+// pack_f_local and g* (FP32), each direction a >= 1 less wg_a tr[a], tr[a]
+// the T_ref of the node that pulls it: its own reference word `own` into
+// direction 0, the (f, g) words of directions 1-8 and the FP32 rest pair.
+__device__ __forceinline__ void store_pairs_local(
+    const StepParams& p, unsigned int* buf, void* rest, int nx, long long y,
+    int x, const unsigned int hf[Q], const float go[Q], const float tr[Q],
+    unsigned int own) {
+  float wt[Q];
+  wt[0] = 0.0f;
+#pragma unroll
+  for (int a = 1; a < Q; ++a) wt[a] = float(w_rest(p, a)) * tr[a];
+  unsigned int hg[Q];
+  float rg;
   half_node_ref(go, wt, hg, rg);
   gbl(buf)[dix(nx, 0, y, x)] = own;
 #pragma unroll
@@ -573,7 +578,7 @@ __device__ __forceinline__ void store_local(const StepParams& p,
     gbl(buf)[dix(nx, a, y, x)] =
         __builtin_amdgcn_perm(hg[a], hf[a], 0x05040100u);
   gbl(static_cast<unsigned long long*>(rest))[y * nx + x] =
-      (unsigned long long)__float_as_uint(rf) |
+      (unsigned long long)hf[0] |
       ((unsigned long long)__float_as_uint(rg) << 32);
 }
 
@@ -620,11 +625,14 @@ __device__ __forceinline__ void cook_f(const StepParams& p, const Shift<P>& sh,
 #pragma unroll
     for (int a = 1; a < Q; ++a)
       f[a] = Prec<4>::cvt(fr[a]) + float(w_lat(a)) * Prec<4>::cvt(gr[a]);
-    if (GEN && !p.fresh) {
+    const bool open = p.bc[0] == BC_OPEN || p.bc[1] == BC_OPEN ||
+                      p.bc[2] == BC_OPEN || p.bc[3] == BC_OPEN;
+    if (GEN && !p.fresh && open) {
       // across an open side the value comes from the clamped source, whose
       // puller is its neighbour x + e_a inside the lattice: the value was
       // stored against that node's reference, read here (waves with an
-      // edge node only)
+      // edge node of a lattice with an open side only: the load is waited
+      // for at once, with the row prefetch in flight)
       const EdgeSides e(p, x, y, true);
       if (__builtin_amdgcn_ballot_w64(e.any()) != 0) {
         const Gbl<unsigned int>* w = gbl(static_cast<const unsigned int*>(p.fin));

@@ -183,30 +183,27 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
     sg[a] = C(p.s_g[a]);
   }
 
-  // node-referenced FP16 form: binary16 rho and T of the nodes that pull
-  // the eight values node (x, y) stores, x + e_a, from the LDS rings (s0,
-  // sU, sD: slots of rows y, y + 1, y - 1, clamped like the stencil's), or
-  // the node's own where e_a leaves the lattice across a wall (a value
-  // leaving across an open side is never pulled); rr[0], tr[0] are its own.
-  auto dest_refs = [&](int s0, int sU, int sD, int x, int y, float rr[Q],
-                       float tr[Q]) __attribute__((always_inline)) {
-    constexpr int SLOT[Q] = {0, 0, 1, 0, 2, 1, 1, 2, 2};  // y, y+1, y-1
+  // node-referenced FP16 form: the reference (binary16 rho or T, from the
+  // ring `ring`) of each node that pulls one of the eight values node (x, y)
+  // stores, x + e_a (s0, sU, sD: ring slots of rows y, y + 1, y - 1,
+  // clamped like the stencil's), or the node's own where e_a leaves the
+  // lattice across a wall (a value leaving across an open side is never
+  // pulled); r[0] is the node's own.
+  auto dest_ref = [&](const C (*ring)[BLOCK], int s0, int sU, int sD, int x,
+                      int y, float r[Q]) __attribute__((always_inline)) {
+    constexpr int ROW[Q] = {0, 0, 1, 0, 2, 1, 1, 2, 2};  // y, y+1, y-1
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-      const int sl = SLOT[a] == 0 ? s0 : (SLOT[a] == 1 ? sU : sD);
+      const int sl = ROW[a] == 0 ? s0 : (ROW[a] == 1 ? sU : sD);
       const int tt = EXs[a] > 0 ? ttp : (EXs[a] < 0 ? ttm : t);
-      rr[a] = ref_round(s_rho[sl][tt]);
-      tr[a] = ref_round(s_T[sl][tt]);
+      r[a] = ref_round(ring[sl][tt]);
     }
     if (GEN) {
       const EdgeSides e(p, x, y, true);
       if (__builtin_amdgcn_ballot_w64(e.any()) != 0) {
 #pragma unroll
         for (int a = 1; a < Q; ++a)
-          if (e.wall(p, OPs[a])) {
-            rr[a] = rr[0];
-            tr[a] = tr[0];
-          }
+          if (e.wall(p, OPs[a])) r[a] = r[0];
       }
     }
   };
@@ -373,8 +370,8 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
 #pragma unroll
         for (int a = 0; a < Q; ++a) fo[a] -= sh.f(a);
         if constexpr (P == 4) {
-#pragma unroll
-          for (int a = 0; a < Q; ++a) hfn[a] = __float_as_uint(fo[a]);
+          const float z[Q] = {};  // (stored values unused)
+          pack_f_local(fo, z, hfn);
         } else if constexpr (Tr::paired) {
           pack_f<P>(fo, hfn);
         } else {
@@ -474,9 +471,9 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
 #pragma unroll
           for (int a = 0; a < Q; ++a) fo[a] -= sh.f(a);
           if constexpr (P == 4) {
-            // f* waits in FP32: its references are taken with g*'s at C2
-#pragma unroll
-            for (int a = 0; a < Q; ++a) hfn[a] = __float_as_uint(fo[a]);
+            float rr[Q];
+            dest_ref(s_rho, sl1, sp, sm, c, rb, rr);
+            pack_f_local(fo, rr, hfn);
           } else if constexpr (Tr::paired) {
             pack_f<P>(fo, hfn);
           } else {
@@ -532,12 +529,8 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
         for (int a = 0; a < Q; ++a) go[a] -= sh.g(a);
         phio[(long long)yc * nx + c] = hphi;
         if constexpr (P == 4) {
-          // (the values stored are not used)
-          float fo[Q];
           const float z[Q] = {};
-#pragma unroll
-          for (int a = 0; a < Q; ++a) fo[a] = __uint_as_float(hf1[a]);
-          store_local(p, fout, p.rout, nx, yc, c, fo, go, z, z, 0u);
+          store_pairs_local(p, fout, p.rout, nx, yc, c, hf1, go, z, 0u);
         } else if constexpr (Tr::paired) {
           store_pairs<P>(fout, p.rout, nx, yc, c, hf1, go);
         } else {
@@ -747,12 +740,10 @@ __device__ __forceinline__ void step_tile(const StepParams& p, int bx, int by,
 #pragma unroll
         for (int a = 0; a < Q; ++a) go[a] -= sh.g(a);
         if constexpr (P == 4) {
-          float fo[Q], rr[Q], tr[Q];
-#pragma unroll
-          for (int a = 0; a < Q; ++a) fo[a] = __uint_as_float(hf1[a]);
-          dest_refs(sl2, sN, sS, c, yc, rr, tr);
-          store_local(p, fout, p.rout, nx, yc, c, fo, go, rr, tr,
-                      ref_word(s_rho[sl2][t], T));
+          float tr[Q];
+          dest_ref(s_T, sl2, sN, sS, c, yc, tr);
+          store_pairs_local(p, fout, p.rout, nx, yc, c, hf1, go, tr,
+                            ref_word(s_rho[sl2][t], T));
         } else if constexpr (Tr::paired) {
           store_pairs<P>(fout, p.rout, nx, yc, c, hf1, go);
         } else {

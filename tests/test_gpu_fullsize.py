@@ -30,9 +30,9 @@ CENTRES = [(0, 0), (241, 35), (252, 70), (4095, 4095), (3856, 4095),
 # measured when they were set (FP64 6.5e-16; FP32 1.4e-7, FP32 deviations
 # 1.5e-7, FP16 deviations 2.2e-4; mass drift 1e-15, 9e-9, 9e-9, 7.8e-7)
 TOL = {I.FP64: 1e-12, I.FP32: 5e-7, I.FP32_SHIFTED: 5e-7,
-       I.FP16_SHIFTED: 7e-4, I.FP16_LOCAL: 7e-4}
+       I.FP16_SHIFTED: 7e-4, I.FP16_LOCAL: 7e-6}
 MASS = {I.FP64: 1e-12, I.FP32: 3e-8, I.FP32_SHIFTED: 3e-8,
-        I.FP16_SHIFTED: 3e-6, I.FP16_LOCAL: 3e-6}
+        I.FP16_SHIFTED: 3e-6, I.FP16_LOCAL: 3e-8}
 
 
 def _split(state):
