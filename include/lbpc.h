@@ -276,8 +276,9 @@ lbpc_status lbpc_autotune(lbpc_handle *h, int32_t steps, int32_t *block_width,
  * march order as lbpc_step) on the current state, which it leaves as it is,
  * and reports the mean milliseconds per launch.  The step moves the same
  * bytes per launch, so its time over this one is the share of the bandwidth
- * its access pattern can reach that it attains.  Periodic lattices only
- * (LBPC_ERR_UNSUPPORTED otherwise).  Blocks until done. */
+ * its access pattern can reach that it attains.  Periodic lattices on
+ * 256- or 512-thread tiles only (LBPC_ERR_UNSUPPORTED otherwise).  Blocks
+ * until done. */
 lbpc_status lbpc_memory_probe(lbpc_handle *h, int32_t launches,
                               double *ms_per_launch);
 

@@ -627,6 +627,10 @@ lbpc_status lbpc_memory_probe(lbpc_handle* h, int32_t launches,
   // reads the current buffer and the phi history; writes the other buffer
   // (which the next step overwrites) and phi to scratch
   StepParams p = params_now(h);
+  // the probe kernel is built for the default block widths only
+  if (p.bw != 256 && p.bw != 512)
+    return fail(h, LBPC_ERR_UNSUPPORTED,
+                "memory probe: 256- or 512-thread tiles only");
   p.phi_out = phi_buf(h, 1 - h->phi_sel);
   hipEvent_t e0, e1;
   HIP_TRY(h, hipEventCreate(&e0), "event");

@@ -99,6 +99,34 @@ def test_smallest_lattice_reduced_precision(prec, sides):
     assert e["rho"] < SHORT[prec] and e["T"] < SHORT[prec], e
 
 
+def test_memory_probe_leaves_the_state_and_refuses_narrow_tiles():
+    """lbpc_memory_probe times the step's memory schedule on the periodic
+    kernel's default block widths and leaves the state as it was; on 64- or
+    128-thread tiles (no probe kernel is built for them) and on a walled
+    lattice it reports LBPC_ERR_UNSUPPORTED."""
+    lb = _lb()
+    cfg, fl = I.static_droplet(300, 40, 10.0)
+    for prec in (I.FP64, I.FP16_LOCAL):
+        g = lb.Simulation(dict(cfg, precision=prec))
+        g.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
+        g.step(3)
+        s0 = g.save_state()
+        assert g.memory_probe(2) > 0.0
+        assert np.array_equal(g.save_state(), s0)
+        for bw in (64, 128):
+            g.set_tiles(bw, 8)
+            with pytest.raises(lb.LbpcError) as e:
+                g.memory_probe(2)
+            assert e.value.status == lb.ERR_UNSUPPORTED
+        g.close()
+    w = lb.Simulation(dict(cfg, bc=[I.BC_WALL] * 4))
+    w.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
+    with pytest.raises(lb.LbpcError) as e:
+        w.memory_probe(2)
+    assert e.value.status == lb.ERR_UNSUPPORTED
+    w.close()
+
+
 def test_zero_steps_change_nothing():
     """lbpc_step with n = 0 (and lbpc_batch_step) leaves state, history and
     step count as they were, and the run continues bitwise as if it had not
