@@ -36,9 +36,9 @@
  * Environment, read when a handle or batch is created (scheduling only:
  * results never depend on it):
  *   LBPC_TILE_BW, LBPC_TILE_H      initial block width and rows per tile
- *   LBPC_TILE_HE                   with LBPC_TILE_H, FP64 only: rows per
- *                                  tile of the two strips holding
- *                                  non-periodic x sides
+ *   LBPC_TILE_HE                   with LBPC_TILE_H, FP64 and FP16 forms
+ *                                  only: rows per tile of the two strips
+ *                                  holding non-periodic x sides
  *   LBPC_XCD_ORDER=0               plain tile order instead of the
  *                                  XCD-aware one
  *   LBPC_GRAPH=1, LBPC_BATCH_GRAPH=1   replay steady steps from a captured
@@ -247,7 +247,8 @@ lbpc_status lbpc_set_tiles(lbpc_handle *h, int32_t block_width, int32_t rows);
 
 /* The tile shape in place: threads per block, rows per tile, and rows per
  * tile of the two strips that hold the x sides when those are not periodic,
- * in FP64 (equal to rows otherwise, and after lbpc_set_tiles).  Any output pointer
+ * in FP64 and the FP16 forms (equal to rows otherwise, and after
+ * lbpc_set_tiles).  Any output pointer
  * may be NULL; LBPC_ERR_ARG if h is NULL.  Host only: no device work. */
 lbpc_status lbpc_get_tiles(const lbpc_handle *h, int32_t *block_width,
                            int32_t *rows, int32_t *rows_edge);

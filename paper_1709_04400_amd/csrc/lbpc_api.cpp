@@ -199,8 +199,12 @@ void set_tiles_impl(lbpc_handle* h, int bw, int rows, int rows_edge) {
   p.bw = bw;
   strip_shape(h->cfg.nx, bw, balanced_strips(h->cfg.precision, bw), p.nbx, p.W);
   p.H = rows;
-  // the step kernels take a separate edge-strip height in FP64 only
-  p.He = h->cfg.precision == LBPC_FP64 ? rows_edge : rows;
+  // the step kernels take a separate edge-strip height in FP64 and the FP16
+  // forms only
+  p.He = h->cfg.precision == LBPC_FP32 ||
+                 h->cfg.precision == LBPC_FP32_SHIFTED
+             ? rows
+             : rows_edge;
   p.nby = (h->cfg.ny + p.H - 1) / p.H;
   if (h->tiled) {
     h->nwork = (int)tile_list(p).size();

@@ -194,13 +194,15 @@ def _with_env(env, fn):
                 os.environ[k] = v
 
 
-@pytest.mark.parametrize("prec", [I.FP64, I.FP32])
+@pytest.mark.parametrize("prec", [I.FP64, I.FP32, I.FP16_SHIFTED,
+                                  I.FP16_LOCAL])
 def test_shorter_runs_in_the_x_edge_strips(prec):
     """Strips holding walls on the x sides with their own run height (13
     rows against 24 elsewhere, 128-thread blocks: 3 strips, so runs of
     different heights meet along both strip boundaries) on a walled
-    boiling cut with a hot spot: the same result as the oracle.  Only FP64
-    takes the separate height; the FP32 forms keep one for every strip."""
+    boiling cut with a hot spot: the same result as the oracle.  FP64 and
+    the FP16 forms take the separate height; the FP32 forms keep one for
+    every strip."""
     cfg, fl = _cut(300, 200, "walls")
     cfg.update(hot_x0=140, hot_x1=160, T_hot=1.1 * I.T_SAT,
                lambda_mode=I.LAMBDA_RHO_CV_CHI, chi=I.CHI_BUBBLE,
@@ -210,7 +212,7 @@ def test_shorter_runs_in_the_x_edge_strips(prec):
     o.step(60)
     g = _with_env({"LBPC_TILE_BW": 128, "LBPC_TILE_H": 24,
                    "LBPC_TILE_HE": 13}, lambda: _lb().Simulation(cfg))
-    edge = 13 if prec == I.FP64 else 24
+    edge = 24 if prec in (I.FP32, I.FP32_SHIFTED) else 13
     assert g.tiles() == {"block_width": 128, "rows": 24, "rows_edge": edge}
     g.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
     g.step(60)
