@@ -7,7 +7,9 @@ no longer touches the wall row (reading C21), and D = 2 sqrt(A / pi) of that
 region.  What is checked is the trend: every g departs, D falls with g, and
 the log-log slope is -0.5 within the scatter of a five-point fit.  The
 constant is not compared (heating and wetting are readings, see the boiling
-builder)."""
+builder).  The same sweep in FP16 storage with node-local references must
+show the same trend, each departure within 5 % of FP64's step and
+diameter."""
 import json
 
 import numpy as np
@@ -21,9 +23,9 @@ pytestmark = pytest.mark.gpu
 GS = [2.0e-5, 2.5e-5, 3.0e-5, 4.0e-5, 5.0e-5]
 
 
-def _departures(gs, max_steps=60000, every=250):
+def _departures(gs, max_steps=60000, every=250, precision=I.FP64):
     from paper_1709_04400_amd import lbpc
-    cases = [I.boiling(g) for g in gs]
+    cases = [I.boiling(g, precision=precision) for g in gs]
     b = lbpc.Batch([c for c, _ in cases])
     for k, (_, f) in enumerate(cases):
         b.init_fields(k, f["rho"], f["ux"], f["uy"], f["T"])
@@ -67,4 +69,17 @@ def test_departure_diameter_falls_like_g_to_minus_half():
     assert np.all(np.diff(D) < 0), D
     slope = np.polyfit(np.log(GS), np.log(D), 1)[0]
     print(f"[departure] log-log slope {slope:.3f}", flush=True)
+    assert -0.65 < slope < -0.35, slope
+
+
+def test_departure_sweep_in_fp16_with_node_local_references():
+    ref = _departures(GS)
+    res = _departures(GS, precision=I.FP16_LOCAL)
+    print("\n[departure] FP16_LOCAL " + json.dumps(res), flush=True)
+    assert all(r is not None for r in res), res
+    for r64, r16 in zip(ref, res):
+        assert abs(r16["step"] - r64["step"]) <= 0.05 * r64["step"], (r64, r16)
+        assert abs(r16["D"] - r64["D"]) <= 0.05 * r64["D"], (r64, r16)
+    slope = np.polyfit(np.log(GS), np.log([r["D"] for r in res]), 1)[0]
+    print(f"[departure] FP16_LOCAL log-log slope {slope:.3f}", flush=True)
     assert -0.65 < slope < -0.35, slope
