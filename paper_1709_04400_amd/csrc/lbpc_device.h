@@ -334,8 +334,9 @@ struct Shift {
 //             non-periodic axes, and a wave holding an edge node takes, for
 //             each wall-crossing direction, f*_abar and g*_abar of the node
 //             itself (branch-free inside the wave).
-//   cook_f,   turn the raw registers into unshifted compute values; cook_g
-//   cook_g    then applies the value rules of g at edge nodes (again only
+//   cook_f,   turn the raw registers into unshifted compute values (the
+//   cook_g    node-referenced FP16 form adds each value's reference); cook_g
+//             then applies the value rules of g at edge nodes (again only
 //             in waves that hold one).
 
 // Distribution buffers interleave the rows of the nine direction arrays,
@@ -635,7 +636,8 @@ __device__ __forceinline__ void cook_f(const StepParams& p, const Shift<P>& sh,
       // for at once, with the row prefetch in flight)
       const EdgeSides e(p, x, y, true);
       if (__builtin_amdgcn_ballot_w64(e.any()) != 0) {
-        const Gbl<unsigned int>* w = gbl(static_cast<const unsigned int*>(p.fin));
+        const Gbl<unsigned int>* w =
+            gbl(static_cast<const unsigned int*>(p.fin));
 #pragma unroll
         for (int a = 1; a < Q; ++a) {
           const bool ox = e.ox(a), oy = e.oy(a);
