@@ -214,17 +214,19 @@ def sessile_droplet(nx, ny, radius, wet_amp=0.0, wet_shift=0.0, T_w=None,
 
 def heated_surface(model=THERMAL_IMPROVED, lambda_mode=LAMBDA_RHO_CV_CHI,
                    nx=300, ny=150, radius=40.0, T_w_over_Tc=0.875,
-                   wet_amp=WET_AMP_SURFACE, precision=FP64):
+                   wet_amp=WET_AMP_SURFACE, top=BC_OPEN, precision=FP64):
     """Droplet evaporation on a heated surface, Sec. IV.A: a 300 x 150
     lattice, a droplet of radius 40 on the centre of the bottom surface at
     T_sat = 0.86 Tc in vapour at T_sat,
     lambda = rho c_V chi with chi = 0.08 (or the constant lambda of the D^2
-    test), nu = 0.1, c_V = 5, periodic x, open top at T_sat.  Returns the
-    configuration of the evaporation stage (bottom wall at T_w = 0.875 Tc);
-    the equilibration stage before it is the same with the wall at T_sat.
-    The wall wets at about 95 degrees (WET_AMP_SURFACE), not the paper's 108."""
+    test), nu = 0.1, c_V = 5, periodic x, open top at T_sat (top=BC_WALL:
+    a closed box, its top wall at T_sat).  Returns the configuration of the
+    evaporation stage (bottom wall at T_w = 0.875 Tc); the equilibration
+    stage before it is the same with the wall at T_sat.  The wall wets at
+    about 95 degrees by default (WET_AMP_SURFACE), not the paper's 108;
+    wet_amp = 0 is the neutral wall (about 90 degrees)."""
     cfg, fl = sessile_droplet(nx, ny, radius, wet_amp=wet_amp,
-                              T_w=T_w_over_Tc * TC, top=BC_OPEN,
+                              T_w=T_w_over_Tc * TC, top=top,
                               precision=precision)
     cfg.update(thermal_model=model, lambda_mode=lambda_mode)
     return cfg, fl

@@ -1,0 +1,98 @@
+"""Droplet evaporation on a heated surface (Sec. IV.A, second test; Fig. 3).
+The paper runs a 300 x 150 lattice with a droplet of radius 40 on the
+bottom wall, lambda = rho c_V chi (chi = 0.08), 20000 equilibration steps
+with the wall at T_sat, then the wall at 0.875 Tc.  It finds that the
+Gong-Cheng model evaporates the droplet more slowly than the compromised
+and the improved models, with the contact line pinned (constant contact
+radius).  Its open top and contact-angle hysteresis are not defined in its
+text, so this set-up reads them (C32): a closed box whose top wall stays at
+T_sat, and the neutral wall (about 90 degrees) with no hysteresis rule.
+
+  * parity: the evaporation stage of each model against the oracle;
+  * the paper's ordering: the Gong-Cheng model loses the least liquid.
+The wetted length of the wall row is reported, not bounded: over these
+runs it moves by a few nodes, too little to tell a pinned contact line from
+one that follows the shrinking droplet."""
+import json
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1709_04400_amd import inputs as I
+from test_gpu_parity import TOL, _errors
+
+pytestmark = pytest.mark.gpu
+
+MODELS = [(I.THERMAL_GONG_CHENG, "Gong-Cheng"),
+          (I.THERMAL_COMPROMISED, "compromised"),
+          (I.THERMAL_IMPROVED, "improved")]
+
+
+def _lb():
+    from paper_1709_04400_amd import lbpc
+    return lbpc
+
+
+def _cfg(model, T_w_over_Tc):
+    return I.heated_surface(model=model, wet_amp=0.0, top=I.BC_WALL,
+                            T_w_over_Tc=T_w_over_Tc)
+
+
+@pytest.mark.parametrize("model", [m for m, _ in MODELS])
+def test_heated_surface_against_the_oracle(model):
+    """200 steps of the evaporation stage (heated wall, closed box) from
+    the initial droplet, FP64, within the parity bound."""
+    cfg, fl = _cfg(model, 0.875)
+    o = O.Oracle(cfg)
+    o.init_fields(**fl)
+    o.step(200)
+    g = _lb().Simulation(cfg)
+    g.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
+    g.step(200)
+    e = _errors(g.rho_u_T(), o.rho_u_T())
+    g.close()
+    print(f"\n[heated surface] parity model={model} {e}", flush=True)
+    assert e["rho"] < TOL and e["T"] < TOL, e
+
+
+def _liquid(sim):
+    r = sim.rho_u_T()[0]
+    liq = r > 0.5 * (I.RHO_L + I.RHO_V)
+    return float(liq.sum()), int(liq[0].sum())
+
+
+def test_gong_cheng_evaporates_slowest_with_variable_conductivity():
+    """After 20000 equilibration steps (wall at T_sat, improved model), each
+    model runs 60000 steps with the wall at 0.875 Tc from the same state.
+    Every droplet loses more than 5 % of its liquid nodes, and the
+    Gong-Cheng model loses at most 0.9 of what either other model loses
+    (measured when the bound was set: 0.63 of the compromised model's loss,
+    0.76 of the improved model's; 179, 284 and 236 of 2458 liquid
+    nodes)."""
+    lb = _lb()
+    cfg, fl = _cfg(I.THERMAL_IMPROVED, I.T_SAT / I.TC)
+    eq = lb.Simulation(cfg)
+    eq.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
+    eq.step(20000)
+    state = eq.save_state()
+    a0, w0 = _liquid(eq)
+    eq.close()
+    out = {"equilibrium": {"liquid_nodes": a0, "wetted_wall_nodes": w0}}
+    for model, name in MODELS:
+        s = lb.Simulation(_cfg(model, 0.875)[0])
+        s.load_state(state)
+        hist = []
+        for _ in range(6):
+            s.step(10000)
+            hist.append(_liquid(s))
+        s.close()
+        out[name] = {"liquid_nodes": [h[0] for h in hist],
+                     "wetted_wall_nodes": [h[1] for h in hist],
+                     "loss": a0 - hist[-1][0]}
+    print("\n[heated surface] " + json.dumps(out), flush=True)
+    for _, name in MODELS:
+        assert out[name]["loss"] > 0.05 * a0, (name, out[name])
+    gc = out["Gong-Cheng"]["loss"]
+    assert gc <= 0.9 * out["compromised"]["loss"], out
+    assert gc <= 0.9 * out["improved"]["loss"], out
