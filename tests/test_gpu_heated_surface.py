@@ -34,9 +34,9 @@ def _lb():
     return lbpc
 
 
-def _cfg(model, T_w_over_Tc):
+def _cfg(model, T_w_over_Tc, precision=I.FP64):
     return I.heated_surface(model=model, wet_amp=0.0, top=I.BC_WALL,
-                            T_w_over_Tc=T_w_over_Tc)
+                            T_w_over_Tc=T_w_over_Tc, precision=precision)
 
 
 @pytest.mark.parametrize("model", [m for m, _ in MODELS])
@@ -62,25 +62,27 @@ def _liquid(sim):
     return float(liq.sum()), int(liq[0].sum())
 
 
-def test_gong_cheng_evaporates_slowest_with_variable_conductivity():
+@pytest.mark.parametrize("prec", [I.FP64, I.FP16_LOCAL])
+def test_gong_cheng_evaporates_slowest_with_variable_conductivity(prec):
     """After 20000 equilibration steps (wall at T_sat, improved model), each
     model runs 60000 steps with the wall at 0.875 Tc from the same state.
     Every droplet loses more than 5 % of its liquid nodes, and the
     Gong-Cheng model loses at most 0.9 of what either other model loses
     (measured when the bound was set: 0.63 of the compromised model's loss,
     0.76 of the improved model's; 179, 284 and 236 of 2458 liquid
-    nodes)."""
+    nodes).  The same in FP16 storage with node-local references."""
     lb = _lb()
-    cfg, fl = _cfg(I.THERMAL_IMPROVED, I.T_SAT / I.TC)
+    cfg, fl = _cfg(I.THERMAL_IMPROVED, I.T_SAT / I.TC, prec)
     eq = lb.Simulation(cfg)
     eq.init_fields(fl["rho"], fl["ux"], fl["uy"], fl["T"])
     eq.step(20000)
     state = eq.save_state()
     a0, w0 = _liquid(eq)
     eq.close()
-    out = {"equilibrium": {"liquid_nodes": a0, "wetted_wall_nodes": w0}}
+    out = {"precision": prec,
+           "equilibrium": {"liquid_nodes": a0, "wetted_wall_nodes": w0}}
     for model, name in MODELS:
-        s = lb.Simulation(_cfg(model, 0.875)[0])
+        s = lb.Simulation(_cfg(model, 0.875, prec)[0])
         s.load_state(state)
         hist = []
         for _ in range(6):
