@@ -225,12 +225,15 @@ def test_autotune_and_tiles_leave_results_unchanged(which):
     g.close()
 
 
+@pytest.mark.parametrize("prec", [I.FP64, I.FP16_LOCAL])
 @pytest.mark.parametrize("which", ["periodic", "walls"])
-def test_graph_replay_equals_eager(monkeypatch, which):
+def test_graph_replay_equals_eager(monkeypatch, which, prec):
     """Steady steps replayed from the captured two-step graph match launches
     one by one, bitwise, through odd step counts, reads, a tile change, an
-    autotune and a save / load."""
-    cfg, fl = I.bubble(nx=200, ny=96, pool=60, hot_width=16, g=3e-5)
+    autotune and a save / load (FP64, and the node-referenced FP16 form with
+    its rest and reference arrays)."""
+    cfg, fl = I.bubble(nx=200, ny=96, pool=60, hot_width=16, g=3e-5,
+                       precision=prec)
     if which == "periodic":
         cfg["bc"] = [I.BC_PERIODIC] * 4
     sims = []
